@@ -1,0 +1,312 @@
+/*
+ * Plain FP64 CPU oracle for the per-particle Lagrangian time step of
+ * SCALE-TRACK (arXiv 2603.26691).  TEST INFRASTRUCTURE ONLY: only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it; the product library never does.  It shares no code with the HIP
+ * implementation.  See st_oracle.h for the definitions it follows.
+ *
+ * Written for a reader checking it against the paper by eye: one particle
+ * at a time, in id order, no blocking, no reordering, no fusion.
+ */
+#include "st_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static const double OR_PI = 3.14159265358979323846;
+
+static double width(const or_mesh *m, int a) { return m->L[a] / m->n[a]; }
+
+static double cell_volume(const or_mesh *m)
+{
+    return width(m, 0) * width(m, 1) * width(m, 2);
+}
+
+static int64_t n_cells(const or_mesh *m)
+{
+    return (int64_t)m->n[0] * m->n[1] * m->n[2];
+}
+
+/* Euclidean remainder: the periodic image of index i on an axis of n cells. */
+static int64_t wrap_index(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Flat index of cell (i, j, k), component c, in a [3][n2][n1][n0] field. */
+static int64_t field_index(const or_mesh *m, int c, int64_t i, int64_t j,
+                           int64_t k)
+{
+    return ((c * (int64_t)m->n[2] + k) * m->n[1] + j) * m->n[0] + i;
+}
+
+void or_cell(const or_mesh *m, const double x[3], int32_t c[3])
+{
+    /* The particle's cell is the one whose half-open interval
+     * [i h, (i+1) h) holds it; a point on a face belongs to the upper cell. */
+    for (int a = 0; a < 3; ++a) {
+        double q = floor(x[a] / width(m, a));
+        c[a] = (int32_t)wrap_index((int64_t)q, m->n[a]);
+    }
+}
+
+void or_cells(const or_mesh *m, int64_t np, const double *x, int32_t *c)
+{
+    for (int64_t p = 0; p < np; ++p) or_cell(m, x + 3 * p, c + 3 * p);
+}
+
+void or_wrap(const or_mesh *m, double x[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (x[a] >= m->L[a]) x[a] -= m->L[a];
+        if (x[a] < 0.0) x[a] += m->L[a];
+        if (x[a] == m->L[a]) x[a] = 0.0;
+    }
+}
+
+double or_tau(const or_mesh *m, double d)
+{
+    /* Stokes response time of a sphere. */
+    return m->rho_p * d * d / (18.0 * m->mu_f);
+}
+
+double or_mass(const or_mesh *m, double d)
+{
+    /* Mass of a parcel of spheres of diameter d. */
+    return m->parcel_weight * m->rho_p * OR_PI * d * d * d / 6.0;
+}
+
+/*
+ * Interpolation stencil at position x: 8 corner cells (x-index fastest in
+ * the corner number), their weights and the weights' gradient with respect
+ * to x.  Trilinear: the cell centres sit at (i + 1/2) h; with
+ * s = x/h - 1/2, i0 = floor(s), f = s - i0 the corner weights along one
+ * axis are (1 - f) for i0 and f for i0 + 1.  Nearest grid point: the
+ * containing cell with weight 1 (the other 7 weights are 0).
+ */
+typedef struct {
+    int64_t cell[8][3];
+    double w[8];
+    double dw[8][3];
+} stencil;
+
+static void make_stencil(const or_mesh *m, const double x[3], stencil *st)
+{
+    if (m->interp == 1) {
+        int32_t c[3];
+        or_cell(m, x, c);
+        memset(st, 0, sizeof *st);
+        for (int k = 0; k < 8; ++k)
+            for (int a = 0; a < 3; ++a) st->cell[k][a] = c[a];
+        st->w[0] = 1.0;
+        return;
+    }
+    int64_t i0[3];
+    double om[3][2], dom[3][2];
+    for (int a = 0; a < 3; ++a) {
+        double h = width(m, a);
+        double s = x[a] / h - 0.5;
+        double fl = floor(s);
+        double f = s - fl;
+        i0[a] = (int64_t)fl;
+        om[a][0] = 1.0 - f;
+        om[a][1] = f;
+        dom[a][0] = -1.0 / h;
+        dom[a][1] = 1.0 / h;
+    }
+    for (int k = 0; k < 8; ++k) {
+        int b[3] = {k & 1, (k >> 1) & 1, (k >> 2) & 1};
+        for (int a = 0; a < 3; ++a)
+            st->cell[k][a] = wrap_index(i0[a] + b[a], m->n[a]);
+        st->w[k] = om[0][b[0]] * om[1][b[1]] * om[2][b[2]];
+        st->dw[k][0] = dom[0][b[0]] * om[1][b[1]] * om[2][b[2]];
+        st->dw[k][1] = om[0][b[0]] * dom[1][b[1]] * om[2][b[2]];
+        st->dw[k][2] = om[0][b[0]] * om[1][b[1]] * dom[2][b[2]];
+    }
+}
+
+void or_interp(const or_mesh *m, const double *Uf, const double x[3],
+               double uf_at_p[3])
+{
+    stencil st;
+    make_stencil(m, x, &st);
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < 8; ++k)
+            acc += st.w[k] * Uf[field_index(m, c, st.cell[k][0],
+                                            st.cell[k][1], st.cell[k][2])];
+        uf_at_p[c] = acc;
+    }
+}
+
+void or_interp_many(const or_mesh *m, const double *Uf, int64_t np,
+                    const double *x, double *uf_at_p)
+{
+    for (int64_t p = 0; p < np; ++p)
+        or_interp(m, Uf, x + 3 * p, uf_at_p + 3 * p);
+}
+
+void or_interp_transpose(const or_mesh *m, const double x[3],
+                         const double a[3], double *Ubar)
+{
+    stencil st;
+    make_stencil(m, x, &st);
+    for (int c = 0; c < 3; ++c)
+        for (int k = 0; k < 8; ++k)
+            Ubar[field_index(m, c, st.cell[k][0], st.cell[k][1],
+                             st.cell[k][2])] += st.w[k] * a[c];
+}
+
+/*
+ * One sub-step of one particle.  Semi-implicit Euler for
+ * m du_p/dt = m (u_f - u_p)/tau + m g:
+ *     u_p' = (tau u_p + dt u_f + tau dt g) / (tau + dt)
+ *     x'   = x + dt u_p'            (wrapped periodically)
+ *     J    = m (u_p' - u_p - g dt)  (drag impulse on the particle)
+ * and the fluid receives -J in the cell that held the particle at the start
+ * of the sub-step: Su_int[c0] -= J / V_cell.
+ */
+static void particle_substep(const or_mesh *m, const double *Uf, double x[3],
+                             double up[3], double d, double dt,
+                             double *Su_int)
+{
+    int32_t c0[3];
+    or_cell(m, x, c0);
+    double ufp[3];
+    or_interp(m, Uf, x, ufp);
+    double tau = or_tau(m, d);
+    double mass = or_mass(m, d);
+    double V = cell_volume(m);
+    double up_new[3], J[3];
+    for (int a = 0; a < 3; ++a) {
+        up_new[a] = (tau * up[a] + dt * ufp[a] + tau * dt * m->g[a]) / (tau + dt);
+        J[a] = mass * (up_new[a] - up[a] - m->g[a] * dt);
+    }
+    for (int a = 0; a < 3; ++a) {
+        x[a] = x[a] + dt * up_new[a];
+        up[a] = up_new[a];
+        Su_int[field_index(m, a, c0[0], c0[1], c0[2])] -= J[a] / V;
+    }
+    or_wrap(m, x);
+}
+
+void or_step(const or_mesh *m, const double *Uf, int64_t np, double *x,
+             double *up, const double *d, double dt, int32_t nsub,
+             double *Su_int)
+{
+    double dts = dt / nsub;
+    for (int32_t s = 0; s < nsub; ++s)
+        for (int64_t p = 0; p < np; ++p)
+            particle_substep(m, Uf, x + 3 * p, up + 3 * p, d[p], dts, Su_int);
+}
+
+void or_run(const or_mesh *m, const double *Uf, int64_t np, double *x,
+            double *up, const double *d, double dt, int32_t nsteps,
+            int32_t nsub, double *Su_int)
+{
+    for (int32_t n = 0; n < nsteps; ++n)
+        or_step(m, Uf, np, x, up, d, dt, nsub, Su_int);
+}
+
+void or_run_rotating(const or_mesh *m, const double *U0, const double *cs,
+                     int64_t np, double *x, double *up, const double *d,
+                     double dt, int32_t nsteps, double *Su_int)
+{
+    int64_t nc = n_cells(m);
+    double *Un = (double *)malloc(sizeof(double) * 3 * nc);
+    if (!Un) return;
+    for (int32_t n = 0; n < nsteps; ++n) {
+        double c = cs[2 * n], s = cs[2 * n + 1];
+        /* Rotation of the velocity vector about the z axis. */
+        for (int64_t q = 0; q < nc; ++q) {
+            double ux = U0[q], uy = U0[nc + q], uz = U0[2 * nc + q];
+            Un[q] = c * ux - s * uy;
+            Un[nc + q] = s * ux + c * uy;
+            Un[2 * nc + q] = uz;
+        }
+        or_step(m, Un, np, x, up, d, dt, 1, Su_int);
+    }
+    free(Un);
+}
+
+int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
+               const double *x0, const double *up0, const double *d,
+               double dt, int32_t nsteps, const double *lambda, double *Ubar,
+               double *dbar)
+{
+    /* Forward pass, keeping the state at the start of every step. */
+    size_t per = (size_t)np * 3;
+    double *xs = (double *)malloc(sizeof(double) * per * (nsteps + 1));
+    double *us = (double *)malloc(sizeof(double) * per * (nsteps + 1));
+    double *scratch = (double *)calloc((size_t)3 * n_cells(m), sizeof(double));
+    if (!xs || !us || !scratch) {
+        free(xs); free(us); free(scratch);
+        return -1;
+    }
+    memcpy(xs, x0, sizeof(double) * per);
+    memcpy(us, up0, sizeof(double) * per);
+    for (int32_t n = 0; n < nsteps; ++n) {
+        memcpy(xs + per * (n + 1), xs + per * n, sizeof(double) * per);
+        memcpy(us + per * (n + 1), us + per * n, sizeof(double) * per);
+        or_step(m, Uf, np, xs + per * (n + 1), us + per * (n + 1), d, dt, 1,
+                scratch);
+    }
+
+    double V = cell_volume(m);
+    for (int64_t p = 0; p < np; ++p) {
+        double xbar[3] = {0, 0, 0}, ubar[3] = {0, 0, 0}, db = 0.0;
+        double tau = or_tau(m, d[p]);
+        double mass = or_mass(m, d[p]);
+        double D = tau + dt;
+        for (int32_t n = nsteps - 1; n >= 0; --n) {
+            const double *x = xs + per * n + 3 * p;
+            const double *up = us + per * n + 3 * p;
+            /* Recompute the forward quantities of this step. */
+            int32_t c0[3];
+            or_cell(m, x, c0);
+            stencil st;
+            make_stencil(m, x, &st);
+            double ufp[3], up_new[3];
+            or_interp(m, Uf, x, ufp);
+            for (int a = 0; a < 3; ++a)
+                up_new[a] = (tau * up[a] + dt * ufp[a] + tau * dt * m->g[a]) / D;
+
+            /* Deposit: Su_int[c0] -= J/V, so Jbar = -lambda[c0] / V. */
+            double Jbar[3], wbar[3], ufbar[3];
+            double mbar = 0.0, taubar = 0.0;
+            for (int a = 0; a < 3; ++a)
+                Jbar[a] = -lambda[field_index(m, a, c0[0], c0[1], c0[2])] / V;
+            for (int a = 0; a < 3; ++a) {
+                /* Everything that reads u_p': the next state's velocity, the
+                 * position update x' = x + dt u_p' and the impulse. */
+                wbar[a] = ubar[a] + dt * xbar[a] + mass * Jbar[a];
+                mbar += Jbar[a] * (up_new[a] - up[a] - m->g[a] * dt);
+                ufbar[a] = dt / D * wbar[a];
+                taubar += wbar[a] * (up[a] + dt * m->g[a] - up_new[a]) / D;
+                ubar[a] = -mass * Jbar[a] + tau / D * wbar[a];
+            }
+            /* Interpolation: u_f(x) = sum_k w_k(x) U[k]. */
+            for (int k = 0; k < 8; ++k) {
+                double dot = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    int64_t q = field_index(m, c, st.cell[k][0], st.cell[k][1],
+                                            st.cell[k][2]);
+                    Ubar[q] += st.w[k] * ufbar[c];
+                    dot += Uf[q] * ufbar[c];
+                }
+                if (m->interp != 1)
+                    for (int a = 0; a < 3; ++a) xbar[a] += st.dw[k][a] * dot;
+            }
+            /* tau = rho_p d^2/(18 mu): dtau/dd = 2 tau/d;
+             * m = w rho_p pi d^3/6:   dm/dd = 3 m/d. */
+            db += taubar * 2.0 * tau / d[p] + mbar * 3.0 * mass / d[p];
+        }
+        dbar[p] = db;
+    }
+    free(xs);
+    free(us);
+    free(scratch);
+    return 0;
+}

@@ -1,0 +1,110 @@
+/*
+ * Plain FP64 CPU oracle for the per-particle Lagrangian time step of
+ * SCALE-TRACK (Schmalfuss, Lesnik, Rusche, Niedermeier, arXiv 2603.26691).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no source, header, constant or helper
+ * with the HIP implementation.
+ *
+ * What is computed (paper, Sec. 2.1 "Governing equations" and Sec. 2.5
+ * "Further implementation details"):
+ *   - Newton's law for a particle, dx_p/dt = u_p and m_p du_p/dt = sum F
+ *     (Sec. 2.1, particle equations of motion), with Stokes drag plus gravity
+ *     as the forces (the paper keeps only drag; gravity and the Stokes limit
+ *     come from the workload definition and are documented readings);
+ *   - semi-implicit Euler: drag implicit, gravity explicit, position advanced
+ *     with the new velocity (Sec. 2.5);
+ *   - the momentum source S_u = (1/V_cell) d(m_p u_p)/dt of Sec. 2.1, read as
+ *     the fluid receiving minus the drag impulse, deposited into the cell
+ *     that contains the particle at the start of the step (Sec. 2.5);
+ *   - fluid velocity at the particle: trilinear interpolation of the
+ *     cell-centred field (default) or the paper's nearest-grid-point scheme
+ *     (Sec. 2.5);
+ *   - a fixed number of sub-steps per call with the field held fixed
+ *     (Sec. 3.3).
+ *
+ * Precision: everything in IEEE binary64; particles processed in id order,
+ * sources summed in id order.  Mesh: n[0] x n[1] x n[2] uniform periodic
+ * cells on [0,L0) x [0,L1) x [0,L2).  Fields are laid out [3][n2][n1][n0]
+ * (component, z, y, x; x fastest).
+ */
+#ifndef ST_ORACLE_H
+#define ST_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n[3];          /* cells per axis */
+    int32_t interp;        /* 0 = trilinear, 1 = nearest grid point */
+    double  L[3];          /* domain extent per axis [m] */
+    double  rho_f;         /* fluid density [kg/m^3] (not used by the drag law) */
+    double  mu_f;          /* fluid dynamic viscosity [Pa s] */
+    double  g[3];          /* gravitational acceleration [m/s^2] */
+    double  rho_p;         /* particle material density [kg/m^3] */
+    double  parcel_weight; /* droplets represented by one parcel (Sec. 3.2) */
+} or_mesh;
+
+/* Cell index of position x along each axis: floor(x_a / h_a) modulo n_a. */
+void or_cell(const or_mesh *m, const double x[3], int32_t c[3]);
+
+/* or_cell for np positions ([np][3] -> [np][3]). */
+void or_cells(const or_mesh *m, int64_t np, const double *x, int32_t *c);
+
+/* Periodic wrap of a position that moved by less than one domain length. */
+void or_wrap(const or_mesh *m, double x[3]);
+
+/* Fluid velocity at x from the cell-centred field Uf ([3][n2][n1][n0]). */
+void or_interp(const or_mesh *m, const double *Uf, const double x[3],
+               double uf_at_p[3]);
+
+/* or_interp for np positions ([np][3] -> [np][3]). */
+void or_interp_many(const or_mesh *m, const double *Uf, int64_t np,
+                    const double *x, double *uf_at_p);
+
+/* Transpose of or_interp: Ubar[corner] += weight * a (per component). */
+void or_interp_transpose(const or_mesh *m, const double x[3],
+                         const double a[3], double *Ubar);
+
+/* Response time tau_p = rho_p d^2 / (18 mu_f) and parcel mass
+ * m_p = w rho_p pi d^3 / 6. */
+double or_tau(const or_mesh *m, double d);
+double or_mass(const or_mesh *m, double d);
+
+/* One call of the Lagrangian step on np particles: nsub sub-steps of dt/nsub
+ * with the field held fixed.  x, up updated in place ([np][3]); the time
+ * integrated momentum source of every sub-step is added to Su_int
+ * ([3][n2][n1][n0]), i.e. Su_int[c0] -= J / V_cell. */
+void or_step(const or_mesh *m, const double *Uf, int64_t np, double *x,
+             double *up, const double *d, double dt, int32_t nsub,
+             double *Su_int);
+
+/* nsteps calls of or_step with the same field. */
+void or_run(const or_mesh *m, const double *Uf, int64_t np, double *x,
+            double *up, const double *d, double dt, int32_t nsteps,
+            int32_t nsub, double *Su_int);
+
+/* nsteps steps with a field that turns about z: step n uses
+ * U^n = R_z(theta_n) U^0 with (cos theta_n, sin theta_n) = cs[2n], cs[2n+1]. */
+void or_run_rotating(const or_mesh *m, const double *U0, const double *cs,
+                     int64_t np, double *x, double *up, const double *d,
+                     double dt, int32_t nsteps, double *Su_int);
+
+/* Reverse-mode derivative of nsteps single-sub-step calls of or_step
+ * starting from (x0, up0), for a loss whose derivative with respect to the
+ * time-integrated source Su_int is lambda ([3][n2][n1][n0]).  Adds dL/dUf to
+ * Ubar ([3][n2][n1][n0]) and writes dL/dd to dbar ([np]).  Returns 0, or -1
+ * if the forward tape could not be allocated. */
+int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
+               const double *x0, const double *up0, const double *d,
+               double dt, int32_t nsteps, const double *lambda, double *Ubar,
+               double *dbar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,416 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle.
+
+Each pin_* takes a loaded oracle and raises AssertionError when the oracle
+disagrees with something the paper or the mathematics fixes:
+  * brute-force cell search (the definition of "the cell containing the
+    particle", paper Sec. 2.5), periodic wrap;
+  * trilinear special cases: exact at cell centres, reproduces fields that
+    are affine in each coordinate, partition of unity, periodic shift
+    invariance; nearest-grid-point returns the containing cell's value;
+  * the discrete closed form of semi-implicit Euler in a uniform field, and
+    first-order convergence to the analytic Stokes-drag solution
+    (Sec. 2.5 states first order);
+  * the textbook Stokes settling speed of a 20 um water droplet in air;
+  * momentum conservation between particles and deposited sources
+    (Sec. 2.1, momentum source), and the start-of-step containing-cell
+    deposit;
+  * the adjoint against central finite differences and the interpolation
+    transpose identity.
+The file also runs as a script (python oracle_pins.py LIB) that reports
+which pins a given build of the oracle fails; the mutant test uses that.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from oracle.oracle import MeshParams, Oracle  # noqa: E402
+
+RHO_P = 1000.0
+MU_F = 1.8e-5
+
+
+def _stokes_tau(d):
+    # From first principles: Stokes drag 3 pi mu d (u - v) on a sphere of
+    # mass rho_p pi d^3 / 6 gives a relaxation time m / (3 pi mu d).
+    mass = RHO_P * math.pi * d ** 3 / 6.0
+    return mass / (3.0 * math.pi * MU_F * d)
+
+
+def _sphere_mass(d, w=1.0):
+    return w * RHO_P * (4.0 / 3.0) * math.pi * (d / 2.0) ** 3
+
+
+def _tg_field(mesh, rng, noise=0.1):
+    nx, ny, nz = mesh.n
+    U = rng.normal(0.0, 1.0, size=(3, nz, ny, nx))
+    zc = (np.arange(nz) + 0.5) / nz
+    yc = (np.arange(ny) + 0.5) / ny
+    xc = (np.arange(nx) + 0.5) / nx
+    U[0] = np.sin(2 * np.pi * xc)[None, None, :] * np.cos(2 * np.pi * yc)[None, :, None] \
+        + noise * U[0]
+    U[1] = -np.cos(2 * np.pi * xc)[None, None, :] * np.sin(2 * np.pi * yc)[None, :, None] \
+        + noise * U[1]
+    U[2] = noise * U[2]
+    return U
+
+
+# ---------------------------------------------------------------------------
+# cells and wrap
+# ---------------------------------------------------------------------------
+def pin_cell_brute_force(orc):
+    rng = np.random.default_rng(11)
+    for n, L in [((8, 8, 8), (1.0, 1.0, 1.0)), ((16, 16, 16), (0.5, 0.5, 0.5)),
+                 ((16, 8, 4), (1.0, 0.5, 0.25)), ((4, 16, 8), (0.25, 2.0, 1.0))]:
+        mesh = MeshParams(n=n, L=L)
+        L_ = np.array(L)
+        x = rng.random((3000, 3)) * L_
+        # exact face positions (dyadic widths make i*h exact)
+        k = 400
+        faces = rng.integers(0, np.array(n), size=(k, 3)) * (L_ / np.array(n))
+        x = np.concatenate([x, faces, np.zeros((1, 3)), np.nextafter(L_, 0)[None, :]])
+        c = orc.cells(mesh, x)
+        for a in range(3):
+            h = L[a] / n[a]
+            lower = np.arange(n[a]) * h
+            # the cell is the last one whose lower face lies at or below x
+            brute = np.count_nonzero(lower[None, :] <= x[:, a][:, None], axis=1) - 1
+            assert np.array_equal(c[:, a], brute), f"cell search axis {a} mesh {n}"
+
+
+def pin_wrap(orc):
+    mesh = MeshParams(n=(8, 8, 8), L=(1.0, 0.5, 0.25), g=(0.0, 0.0, 0.0))
+    U = np.zeros(mesh.field_shape)
+    vel = np.array([2.0, -1.5, 1.0])
+    for a in range(3):
+        U[a] = vel[a]
+    dt = 0.01
+    x0 = np.array([[1.0 - 0.005, 0.004, 0.25 - 0.001],
+                   [0.5, 0.25, 0.125]])
+    up0 = np.tile(vel, (2, 1))
+    d = np.array([20e-6, 20e-6])
+    x1, up1, _ = orc.run(mesh, U, x0, up0, d, dt, 1)
+    L = np.array(mesh.L)
+    expect = np.mod(x0 + dt * vel, L)
+    assert np.all(x1 >= 0) and np.all(x1 < L), "wrapped position outside the box"
+    assert np.allclose(x1, expect, rtol=0, atol=1e-12), "periodic wrap"
+    assert x1[0, 0] < 0.1 and x1[0, 1] > 0.4 and x1[0, 2] < 0.1, "crossing particle not wrapped"
+
+
+# ---------------------------------------------------------------------------
+# interpolation
+# ---------------------------------------------------------------------------
+def pin_interp_cell_centre(orc):
+    rng = np.random.default_rng(12)
+    mesh = MeshParams(n=(8, 4, 16), L=(1.0, 0.5, 2.0))
+    U = rng.normal(size=mesh.field_shape)
+    idx = np.stack([rng.integers(0, mesh.n[a], 200) for a in range(3)], axis=1)
+    x = (idx + 0.5) * mesh.h
+    got = orc.interp(mesh, U, x)
+    want = U[:, idx[:, 2], idx[:, 1], idx[:, 0]].T
+    assert np.array_equal(got, want), "trilinear value at a cell centre"
+
+
+def pin_interp_affine(orc):
+    rng = np.random.default_rng(13)
+    mesh = MeshParams(n=(8, 16, 4), L=(1.0, 2.0, 0.5))
+    h = mesh.h
+    coef = rng.normal(size=(3, 4))  # per component: a + b x + c y + e z
+    nx, ny, nz = mesh.n
+    xc = (np.arange(nx) + 0.5) * h[0]
+    yc = (np.arange(ny) + 0.5) * h[1]
+    zc = (np.arange(nz) + 0.5) * h[2]
+    U = np.empty(mesh.field_shape)
+    for c in range(3):
+        U[c] = (coef[c, 0] + coef[c, 1] * xc[None, None, :] + coef[c, 2] * yc[None, :, None]
+                + coef[c, 3] * zc[:, None, None])
+    L = np.array(mesh.L)
+    x = h / 2 + rng.random((500, 3)) * (L - h)  # between the first and last centres
+    got = orc.interp(mesh, U, x)
+    want = coef[:, 0][None, :] + x @ coef[:, 1:].T
+    assert np.allclose(got, want, rtol=0, atol=1e-12), "affine field reproduction"
+    ones = np.ones(mesh.field_shape)
+    xa = rng.random((500, 3)) * L
+    assert np.allclose(orc.interp(mesh, ones, xa), 1.0, rtol=0, atol=1e-14), "partition of unity"
+
+
+def pin_interp_shift(orc):
+    rng = np.random.default_rng(14)
+    mesh = MeshParams(n=(8, 8, 8), L=(1.0, 1.0, 1.0))
+    U = rng.normal(size=mesh.field_shape)
+    h = mesh.h
+    # positions in the first half cell, where the stencil wraps to the last cell
+    x = rng.random((300, 3)) * (h / 2)
+    base = orc.interp(mesh, U, x)
+    for a in range(3):
+        # shifting the field by one cell along axis a and the position by h
+        # must give the same value
+        Ur = np.roll(U, 1, axis=3 - a)
+        xs = x.copy()
+        xs[:, a] += h[a]
+        assert np.allclose(orc.interp(mesh, Ur, xs), base, rtol=0, atol=1e-13), \
+            f"periodic shift invariance axis {a}"
+        # and a position one full period away interpolates identically
+        xw = x.copy()
+        xw[:, a] += mesh.L[a]
+        assert np.allclose(orc.interp(mesh, U, xw), base, rtol=0, atol=1e-13), \
+            f"period invariance axis {a}"
+
+
+def pin_interp_ngp(orc):
+    rng = np.random.default_rng(15)
+    mesh = MeshParams(n=(8, 4, 16), L=(1.0, 0.5, 2.0), interp=1)
+    U = rng.normal(size=mesh.field_shape)
+    x = rng.random((300, 3)) * np.array(mesh.L)
+    idx = np.floor(x / mesh.h).astype(int)
+    got = orc.interp(mesh, U, x)
+    want = U[:, idx[:, 2], idx[:, 1], idx[:, 0]].T
+    assert np.array_equal(got, want), "nearest grid point takes the containing cell"
+
+
+def pin_interp_transpose(orc):
+    rng = np.random.default_rng(16)
+    mesh = MeshParams(n=(8, 4, 16), L=(1.0, 0.5, 2.0))
+    U = rng.normal(size=mesh.field_shape)
+    x = rng.random((200, 3)) * np.array(mesh.L)
+    a = rng.normal(size=(200, 3))
+    lhs = float(np.sum(orc.interp(mesh, U, x) * a))
+    rhs = float(np.sum(U * orc.interp_transpose(mesh, x, a)))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs)), "<interp U, a> = <U, interp^T a>"
+
+
+# ---------------------------------------------------------------------------
+# time integration
+# ---------------------------------------------------------------------------
+def _min_image(dx, L):
+    return dx - np.round(dx / L) * L
+
+
+def pin_closed_form_uniform(orc):
+    rng = np.random.default_rng(17)
+    mesh = MeshParams(n=(16, 16, 16), L=(0.1, 0.1, 0.1), rho_p=RHO_P, mu_f=MU_F)
+    u = np.array([0.3, -0.2, 0.1])
+    U = np.empty(mesh.field_shape)
+    for a in range(3):
+        U[a] = u[a]
+    P = 12
+    x0 = rng.random((P, 3)) * 0.1
+    up0 = rng.normal(0, 0.5, size=(P, 3))
+    d = np.exp(rng.normal(math.log(20e-6), 0.4, size=P))
+    g = np.array(mesh.g)
+    L = np.array(mesh.L)
+    for dt, nsteps, nsub in [(1e-4, 50, 1), (5e-4, 10, 5)]:
+        x, up, S = orc.run(mesh, U, x0, up0, d, dt, nsteps, nsub)
+        n = nsteps * nsub
+        ds = dt / nsub
+        t = n * ds
+        for p in range(P):
+            tau = _stokes_tau(d[p])
+            r = tau / (tau + ds)
+            vinf = u + g * tau
+            v_n = vinf + (up0[p] - vinf) * r ** n
+            x_n = x0[p] + vinf * t + tau * (up0[p] - vinf) * (1 - r ** n)
+            assert np.allclose(up[p], v_n, rtol=0, atol=1e-12), "closed-form velocity"
+            assert np.all(np.abs(_min_image(x[p] - x_n, L)) < 1e-12), "closed-form position"
+        V = np.prod(L / np.array(mesh.n))
+        impulse = sum(_sphere_mass(d[p]) * (up[p] - up0[p] - g * t) for p in range(P))
+        total = S.reshape(3, -1).sum(axis=1) * V
+        assert np.allclose(total, -impulse, rtol=1e-12, atol=1e-30), "closed-form source total"
+
+
+def pin_terminal_velocity(orc):
+    # A 20 um water droplet in still air settles at about 1.21 cm/s under
+    # Stokes' law (textbook cloud-physics value); horizontally it is carried
+    # with the air.
+    mesh = MeshParams(n=(8, 8, 8), L=(0.1, 0.1, 0.1), rho_p=RHO_P, mu_f=MU_F)
+    U = np.zeros(mesh.field_shape)
+    U[0] = 0.5
+    x, up, _ = orc.run(mesh, U, np.array([[0.05, 0.05, 0.05]]), np.zeros((1, 3)),
+                       np.array([20e-6]), 1e-4, 3000)
+    assert abs(up[0, 2] + 0.01211) < 2e-5, f"Stokes settling speed {up[0, 2]}"
+    assert abs(up[0, 0] - 0.5) < 1e-9 and abs(up[0, 1]) < 1e-12, "carried by the air"
+
+
+def pin_first_order(orc):
+    mesh = MeshParams(n=(8, 8, 8), L=(0.1, 0.1, 0.1), rho_p=RHO_P, mu_f=MU_F)
+    u = np.array([0.2, 0.0, -0.1])
+    U = np.empty(mesh.field_shape)
+    for a in range(3):
+        U[a] = u[a]
+    d = 30e-6
+    tau = _stokes_tau(d)
+    v0 = np.array([1.0, 0.5, 0.0])
+    g = np.array(mesh.g)
+    t_end = 2 * tau
+    exact = u + g * tau + (v0 - u - g * tau) * math.exp(-t_end / tau)
+    errs = []
+    for k in (8, 16, 32, 64):
+        dt = tau / k
+        _, up, _ = orc.run(mesh, U, np.array([[0.05, 0.05, 0.05]]), v0[None, :],
+                           np.array([d]), dt, 2 * k)
+        errs.append(np.max(np.abs(up[0] - exact)))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(0.9 < s < 1.1 for s in slopes), f"first-order convergence, slopes {slopes}"
+
+
+# ---------------------------------------------------------------------------
+# deposit
+# ---------------------------------------------------------------------------
+def _conservation_case(orc, g):
+    rng = np.random.default_rng(18)
+    mesh = MeshParams(n=(16, 12, 8), L=(0.1, 0.06, 0.05), g=g, rho_p=RHO_P, mu_f=MU_F,
+                      parcel_weight=3.0)
+    U = _tg_field(mesh, rng)
+    P = 1500
+    x0 = rng.random((P, 3)) * np.array(mesh.L)
+    up0 = rng.normal(0, 0.3, size=(P, 3))
+    d = np.exp(rng.normal(math.log(20e-6), 0.4, size=P))
+    nsteps, dt = 6, 2e-4
+    x, up, S = orc.run(mesh, U, x0, up0, d, dt, nsteps)
+    V = np.prod(np.array(mesh.L) / np.array(mesh.n))
+    m = np.array([_sphere_mass(dd, 3.0) for dd in d])
+    dP = (m[:, None] * (up - up0)).sum(axis=0)
+    scale = np.abs(m[:, None] * (up - up0)).sum(axis=0)
+    gterm = nsteps * dt * np.array(g) * m.sum()
+    resid = S.reshape(3, -1).sum(axis=1) * V + dP - gterm
+    return resid, scale
+
+
+def pin_conservation(orc):
+    resid, scale = _conservation_case(orc, (0.0, 0.0, -9.81))
+    assert np.all(np.abs(resid) <= 1e-12 * scale), f"momentum balance {resid / scale}"
+    resid, scale = _conservation_case(orc, (0.0, 0.0, 0.0))
+    assert np.all(np.abs(resid) <= 1e-12 * scale), f"deposit = -d(momentum) {resid / scale}"
+
+
+def pin_start_cell_deposit(orc):
+    mesh = MeshParams(n=(16, 16, 16), L=(0.1, 0.1, 0.1), g=(0.0, 0.0, 0.0))
+    h = 0.1 / 16
+    U = np.zeros(mesh.field_shape)
+    U[0] = 1.0
+    x0 = np.array([[3 * h - 1e-9, 5.5 * h, 7.5 * h]])
+    up0 = np.array([[2.0, 0.0, 0.0]])
+    x, up, S = orc.run(mesh, U, x0, up0, np.array([20e-6]), 1e-4, 1)
+    assert math.floor(x[0, 0] / h) == 3, "the particle crossed the face"
+    nz = np.argwhere(S != 0)
+    assert nz.shape[0] == 1 and tuple(nz[0]) == (0, 7, 5, 2), \
+        f"deposit goes to the start-of-step cell, got {nz.tolist()}"
+
+
+def pin_rotating_field(orc):
+    rng = np.random.default_rng(19)
+    mesh = MeshParams(n=(8, 8, 8), L=(0.1, 0.1, 0.1))
+    U0 = _tg_field(mesh, rng)
+    P = 200
+    x0 = rng.random((P, 3)) * 0.1
+    up0 = np.zeros((P, 3))
+    d = np.exp(rng.normal(math.log(20e-6), 0.4, size=P))
+    dt = 1e-4
+    # steps at 0, 90, 180 degrees: the rotated field is exact in binary64
+    cs = np.array([1.0, 0.0, 0.0, 1.0, -1.0, 0.0])
+    xr, ur, Sr = orc.run_rotating(mesh, U0, cs, x0, up0, d, dt, 3)
+    fields = [U0, np.stack([-U0[1], U0[0], U0[2]]), np.stack([-U0[0], -U0[1], U0[2]])]
+    x, up, S = x0, up0, None
+    for F in fields:
+        x, up, S = orc.run(mesh, F, x, up, d, dt, 1, Su_int=S)
+    assert np.array_equal(xr, x) and np.array_equal(ur, up) and np.array_equal(Sr, S), \
+        "rotating-field schedule"
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+def _adjoint_case():
+    rng = np.random.default_rng(20)
+    mesh = MeshParams(n=(8, 8, 8), L=(0.01, 0.01, 0.01), rho_p=RHO_P, mu_f=MU_F,
+                      parcel_weight=2.0)
+    U = _tg_field(mesh, rng, noise=0.3)
+    P = 6
+    x0 = rng.random((P, 3)) * 0.01
+    up0 = rng.normal(0, 0.3, size=(P, 3))
+    d = np.exp(rng.normal(math.log(30e-6), 0.3, size=P))
+    return mesh, U, x0, up0, d
+
+
+def _loss_and_cells(orc, mesh, U, x0, up0, d, dt, nsteps, T):
+    x, up, S = x0, up0, None
+    cells = []
+    for _ in range(nsteps):
+        cells.append(orc.cells(mesh, x))
+        x, up, S = orc.run(mesh, U, x, up, d, dt, 1, Su_int=S)
+    return float(np.sum((S - T) ** 2)), S, np.stack(cells)
+
+
+def pin_adjoint_fd(orc):
+    mesh, U, x0, up0, d = _adjoint_case()
+    dt, nsteps = 2e-4, 6
+    L0, S, cells = _loss_and_cells(orc, mesh, U, x0, up0, d, dt, nsteps, 0.0)
+    rng = np.random.default_rng(21)
+    T = S * (1.0 + 0.3 * rng.normal(size=S.shape))
+    L0, S, cells = _loss_and_cells(orc, mesh, U, x0, up0, d, dt, nsteps, T)
+    lam = 2.0 * (S - T)
+    Ubar, dbar = orc.adjoint(mesh, U, x0, up0, d, dt, nsteps, lam)
+    checked = 0
+    for p in range(d.shape[0]):
+        h = 1e-4 * d[p]
+        dp, dm = d.copy(), d.copy()
+        dp[p] += h
+        dm[p] -= h
+        Lp, _, cp = _loss_and_cells(orc, mesh, U, x0, up0, dp, dt, nsteps, T)
+        Lm, _, cm = _loss_and_cells(orc, mesh, U, x0, up0, dm, dt, nsteps, T)
+        if not (np.array_equal(cp, cells) and np.array_equal(cm, cells)):
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - dbar[p]) <= 1e-5 * abs(fd) + 1e-9 * np.abs(dbar).max(), \
+            f"dL/dd particle {p}: fd {fd} adjoint {dbar[p]}"
+        checked += 1
+    assert checked >= 4, "too few diameter FD samples"
+    # field entries in the stencils of the particles
+    flat = np.argsort(-np.abs(Ubar).ravel())[:20]
+    for q in flat:
+        idx = np.unravel_index(q, Ubar.shape)
+        h = 1e-4
+        Up, Um = U.copy(), U.copy()
+        Up[idx] += h
+        Um[idx] -= h
+        Lp, _, cp = _loss_and_cells(orc, mesh, Up, x0, up0, d, dt, nsteps, T)
+        Lm, _, cm = _loss_and_cells(orc, mesh, Um, x0, up0, d, dt, nsteps, T)
+        if not (np.array_equal(cp, cells) and np.array_equal(cm, cells)):
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - Ubar[idx]) <= 1e-5 * abs(fd) + 1e-9 * np.abs(Ubar).max(), \
+            f"dL/dU {idx}: fd {fd} adjoint {Ubar[idx]}"
+        checked += 1
+    assert checked >= 20, "too few field FD samples"
+
+
+ALL_PINS = [
+    pin_cell_brute_force, pin_wrap, pin_interp_cell_centre, pin_interp_affine,
+    pin_interp_shift, pin_interp_ngp, pin_interp_transpose, pin_closed_form_uniform,
+    pin_terminal_velocity, pin_first_order, pin_conservation, pin_start_cell_deposit,
+    pin_rotating_field, pin_adjoint_fd,
+]
+
+
+def run_all(orc):
+    """Returns the names of the pins this oracle build fails."""
+    failed = []
+    for pin in ALL_PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin(orc)
+        except AssertionError:
+            failed.append(pin.__name__)
+    return failed
+
+
+if __name__ == "__main__":
+    failed = run_all(Oracle(sys.argv[1]))
+    print(",".join(failed) if failed else "ALL_PASSED")
+    sys.exit(0)
