@@ -1,0 +1,178 @@
+/*
+ * scaletrack: the per-particle Lagrangian time step of SCALE-TRACK
+ * (Schmalfuss, Lesnik, Rusche, Niedermeier, arXiv 2603.26691) as a C-ABI
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The library tracks point particles ("parcels", paper Sec. 3.2) through a
+ * given cell-centred fluid velocity field on a uniform periodic Cartesian
+ * mesh and returns the momentum source they feed back to the fluid
+ * (paper Sec. 2.1, particle equations of motion and momentum source; Sec. 2.5,
+ * what the Lagrangian solver needs from and returns to the Eulerian solver).
+ * One call of st_step, per particle:
+ *   1. gathers the fluid velocity at the particle (trilinear interpolation of
+ *      the cell-centred field, or the paper's nearest-grid-point scheme,
+ *      Sec. 2.5);
+ *   2. integrates m du_p/dt = m (u_f - u_p)/tau + m g with semi-implicit
+ *      Euler (drag implicit, gravity explicit, position with the new
+ *      velocity; Sec. 2.5), tau = rho_p d^2 / (18 mu_f) (Stokes drag);
+ *   3. moves the particle (periodic wrap) and re-bins it into its new cell
+ *      and 8^3-cell chunk;
+ *   4. deposits the reacting momentum, minus the drag impulse
+ *      J = m (u_p' - u_p - g dt), divided by the cell volume, into the cell
+ *      that held the particle at the start of the step (Sec. 2.1 momentum
+ *      source, Sec. 2.5 deposit into the containing cell).
+ *
+ * Conventions for every entry point:
+ *   - Return value is an st_status.  Argument errors are detected on the
+ *     host, before anything is enqueued, and leave the state unchanged;
+ *     st_last_error(ctx) then holds a message.  No exception or abort crosses
+ *     this boundary.  A failed HIP call surfaces as ST_ERR_DEVICE.
+ *   - Work is ordered on the caller's HIP stream (hip_stream, a hipStream_t;
+ *     NULL = the default stream).  Pointers passed in are borrowed until the
+ *     stream has reached the call's completion.  Outputs go to caller-owned
+ *     buffers.
+ *   - "on_device" non-zero means the pointer is device memory on the
+ *     context's device; zero means host memory (the call then synchronises
+ *     the stream before returning).
+ *   - Fields are [3][n2][n1][n0]: component, z, y, x, with x fastest.
+ *     Positions and velocities are [count][3].  Particle order inside the
+ *     library is private; everything user visible is indexed by the particle
+ *     id, which is the injection order (0, 1, 2, ...).
+ *   - One context per host thread; the library is not internally
+ *     thread-safe.
+ */
+#ifndef SCALETRACK_ST_H
+#define SCALETRACK_ST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct st_ctx st_ctx; /* opaque; owns every device buffer it uses */
+
+typedef enum {
+    ST_OK = 0,
+    ST_ERR_INVALID = 1,   /* bad argument; nothing was enqueued */
+    ST_ERR_OOM = 2,       /* device allocation failed */
+    ST_ERR_DEVICE = 3,    /* a HIP call failed */
+    ST_ERR_STATE = 4,     /* call not valid in the current state */
+    ST_ERR_CAPACITY = 5   /* particle count would exceed the capacity */
+} st_status;
+
+typedef enum {
+    /* particle state, field, interpolation and sources in binary64 */
+    ST_FORM_FP64 = 0,
+    /* particle state and interpolation in binary32, positions stored as
+     * chunk-local offsets (the chunk origin is exact, implied by the chunk
+     * index); impulses, source accumulation and totals in binary64 */
+    ST_FORM_FP32_LOCAL = 1,
+    /* everything in binary32, sources included */
+    ST_FORM_FP32 = 2
+} st_form;
+
+typedef struct {
+    int32_t n[3];          /* cells per axis; each a multiple of chunk_edge */
+    int32_t chunk_edge;    /* cells per chunk edge: 2, 4 or 8 */
+    double  L[3];          /* domain extent per axis [m]; origin at 0; periodic */
+    double  rho_f;         /* fluid density [kg/m^3] (kept for the record) */
+    double  mu_f;          /* fluid dynamic viscosity [Pa s], > 0 */
+    double  g[3];          /* gravitational acceleration [m/s^2] */
+    double  rho_p;         /* particle material density [kg/m^3], > 0 */
+    double  parcel_weight; /* droplets per parcel (paper Sec. 3.2), > 0 */
+    int32_t form;          /* an st_form */
+    int32_t interp;        /* 0 = trilinear (default), 1 = nearest grid point */
+    int64_t capacity;      /* maximum number of particles, >= 1 */
+} st_mesh_desc;
+
+/* Creates a context on HIP device `device` and allocates, once, every
+ * buffer a run of up to desc->capacity particles needs.  *out receives the
+ * context.  ST_ERR_INVALID for a bad descriptor, ST_ERR_OOM when the device
+ * cannot hold the buffers. */
+st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out);
+
+/* Frees every buffer of the context (after synchronising its device). */
+st_status st_destroy(st_ctx *ctx);
+
+/* Message describing the last error of this context ("" if none). */
+const char *st_last_error(const st_ctx *ctx);
+
+/* Adds n particles: x, up [n][3] (positions in [0,L) per axis, velocities),
+ * d [n] (diameters > 0), all binary64.  Positions outside the box are
+ * wrapped periodically.  New ids continue the injection order.  Host
+ * arrays are validated on the host (non-finite values or d <= 0 give
+ * ST_ERR_INVALID); device arrays are validated on the device and the call
+ * waits for the result.  ST_ERR_CAPACITY if the count would exceed the
+ * capacity (state unchanged). */
+st_status st_inject(st_ctx *ctx, int64_t n, const double *x, const double *up,
+                    const double *d, int on_device, void *hip_stream);
+
+/* Number of particles in the context. */
+st_status st_count(const st_ctx *ctx, int64_t *n);
+
+/* Advances every particle by dt with nsub sub-steps of dt/nsub, the field
+ * u_cells (device memory, [3][n2][n1][n0], binary64 for ST_FORM_FP64 and
+ * binary32 otherwise) held fixed (paper Sec. 3.3, sub-steps).  Each
+ * sub-step adds its deposit to the context's time-integrated source.
+ * tape != 0 records the step for st_backward: the field pointer is then
+ * borrowed until st_backward or st_tape_clear; a checkpoint of the
+ * particle state is kept every `tape` sub-steps (the value of the first
+ * taped call fixes the interval).  dt must be finite and > 0, nsub >= 1. */
+st_status st_step(st_ctx *ctx, const void *u_cells, double dt, int32_t nsub,
+                  int32_t tape, void *hip_stream);
+
+/* Copies the time-integrated momentum source, sum over sub-steps of
+ * S_u dt [kg/(m^2 s)] = -(sum of impulses J) / V_cell per cell, as binary64
+ * [3][n2][n1][n0] into out.  reset != 0 zeroes the context's accumulator
+ * afterwards. */
+st_status st_get_sources(st_ctx *ctx, double *out, int32_t reset,
+                         int on_device, void *hip_stream);
+
+/* Copies the particle state, indexed by id, into any of the non-NULL
+ * outputs: x, up [count][3] binary64 (positions in [0,L)), d [count]
+ * binary64, id [count] int64 (id[i] = i once the copy is complete, a
+ * check of the permutation), cell [count][3] int32 (cell per axis). */
+st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
+                           int64_t *id, int32_t *cell, int on_device,
+                           void *hip_stream);
+
+/* Reverse-mode derivative of the taped steps.  dL_dSint (device,
+ * [3][n2][n1][n0] binary64) is the derivative of a scalar loss with respect
+ * to the time-integrated source accumulated by the taped steps.  Writes
+ * dL/du (device, [3][n2][n1][n0] binary64; the sum over the taped steps'
+ * fields, which are one tensor when every step used the same field) and
+ * dL/dd (device, [count] binary64, by id).  Checkpoints are restored and
+ * the steps between them recomputed.  The tape is consumed.  ST_ERR_STATE
+ * if nothing is taped. */
+st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,
+                      double *dL_dd, void *hip_stream);
+
+/* Drops the tape without differentiating. */
+st_status st_tape_clear(st_ctx *ctx);
+
+/* Asynchronously coupled run (paper Sec. 2.3, at most one step of lag):
+ * nsteps steps of dt in which step k uses the field
+ * U^k = R_z(theta_k) U^0, rotated about z with (cos, sin) of theta_k given
+ * in cs[2k], cs[2k+1] (host memory).  A second stream owned by the context
+ * builds U^(k+1) while the particles step with U^k; events hold the lag at
+ * exactly one step.  u0 is device memory in the form's field precision.
+ * field_ms (host, may be NULL) receives the summed device time of the
+ * field updates and step_ms that of the particle steps, measured with HIP
+ * events on the respective streams; total_ms the wall time from the first
+ * launch to the last completion (the call synchronises when any of the
+ * three is non-NULL). */
+st_status st_run_coupled(st_ctx *ctx, const void *u0, const double *cs,
+                         int32_t nsteps, double dt, float *field_ms,
+                         float *step_ms, float *total_ms, void *hip_stream);
+
+/* Counters of the last st_step (host memory): movers, full repacks so far,
+ * particles, store slots.  Any pointer may be NULL.  Synchronises the
+ * stream. */
+st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
+                   int64_t *particles, int64_t *slots, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

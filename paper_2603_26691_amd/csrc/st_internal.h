@@ -1,0 +1,152 @@
+// Internal declarations of the scaletrack HIP library (not part of the ABI).
+//
+// Particle store: structure of arrays, kept sorted by chunk (a cube of
+// E^3 cells, E = chunk_edge).  Chunk c owns the slot range
+// [base[c], base[c] + room[c]); its cnt[c] live particles sit densely at
+// the start of that range.  Positions are stored as chunk-local offsets in
+// cell units, xi in [0, E) per axis; the chunk origin is exact (the chunk
+// index times E cells).  Two such stores exist; which one is current is
+// held on the device (views[*cur]) so that a re-bin decided on the device
+// never needs the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "st.h"
+
+namespace st {
+
+constexpr int kBlock = 256;       // threads per workgroup of the step kernels
+constexpr int kSeg = 16384;       // max particles per step work item
+constexpr int kSlackMin = 32;     // spare slots per chunk at least (capacity sizing)
+
+template <class T>
+struct View {
+    T *ox, *oy, *oz;   // chunk-local offsets [cells]
+    T *vx, *vy, *vz;   // velocity [m/s]
+    T *d;              // diameter [m]
+    int32_t *id;       // particle id; -1-id marks a slot vacated this step
+    int64_t *base;     // [C] first slot of the chunk
+    int32_t *room;     // [C] slots owned by the chunk
+    int32_t *cnt;      // [C] live particles of the chunk
+};
+
+// Particles in flight between chunks (also the staging area of st_inject).
+template <class T>
+struct Movers {
+    T *ox, *oy, *oz, *vx, *vy, *vz, *d;
+    int32_t *id;
+    int32_t *dest;     // destination chunk
+    int32_t *rank;     // arrival rank within the destination chunk
+};
+
+// Scalars of the mesh and material used by the kernels.
+struct Params {
+    int32_t n[3];          // cells per axis
+    int32_t nc[3];         // chunks per axis
+    int32_t E;             // chunk edge
+    int32_t interp;        // 0 trilinear, 1 nearest grid point
+    int64_t C;             // chunks
+    double L[3];           // domain extent
+    double h[3];           // cell widths
+    double inv_h[3];
+    double inv_V;          // 1 / cell volume
+    double g[3];
+    double tau_coef;       // rho_p / (18 mu_f): tau = tau_coef d^2
+    double mass_coef;      // w rho_p pi / 6:    m = mass_coef d^3
+};
+
+// Flags and counters on the device (one int32 each).
+enum DevFlag { F_OVERFLOW = 0, F_NMOV = 1, F_NITEMS = 2, F_FORCE = 3, F_BADINPUT = 4,
+               F_REPACKS = 5, F_COUNT = 8 };
+
+struct TapeStep {
+    const void *u;     // field of the step (borrowed)
+    double dt;         // sub-step length
+};
+
+struct Snapshot {      // particle store and layout at a checkpoint
+    void *buf = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace st
+
+struct st_ctx {
+    st_mesh_desc desc;
+    st::Params prm;
+    int device = 0;
+    int form = 0;
+    size_t tsize = 8;          // bytes of the state scalar
+    size_t asize = 8;          // bytes of the source accumulator
+    int64_t C = 0;             // chunks
+    int64_t cap = 0;           // particle capacity
+    int64_t slots = 0;         // slots per store
+    int64_t mcap = 0;          // mover / staging capacity
+    int64_t max_items = 0;     // upper bound of step work items
+    int64_t count = 0;         // particles in the store (host mirror)
+    int64_t pending = 0;       // injected particles waiting in the staging area
+    int64_t next_id = 0;
+
+    // device memory
+    void *store[2][8] = {};    // SoA arrays of both stores
+    int64_t *base[2] = {};
+    int32_t *room[2] = {};
+    int32_t *cnt[2] = {};
+    void *views = nullptr;     // View<T>[2]
+    int32_t *cur = nullptr;    // index of the current store
+    void *mov[10] = {};        // Movers arrays
+    int32_t *out_cnt = nullptr, *in_cnt = nullptr;
+    int32_t *in_off = nullptr;     // [C+1]
+    int32_t *cursor = nullptr;     // [C] scatter cursors of the full re-bin
+    int32_t *new_cnt = nullptr;    // [C]
+    int64_t *nbase = nullptr;      // [C+1] first slots of the re-binned layout
+    int32_t *nroom = nullptr;      // [C]   rooms of the re-binned layout
+    int32_t *hole = nullptr;       // [slots]
+    int32_t *inbox = nullptr;      // [mcap]
+    int32_t *items = nullptr;      // [max_items][2]
+    int32_t *nseg = nullptr;       // [C+1]
+    int64_t *scan_tmp = nullptr;   // block partials of the scans
+    int32_t *flags = nullptr;      // DevFlag counters
+    void *src = nullptr;           // [C][3][E^3] accumulator (double or float)
+    double *stage64 = nullptr;     // staging for host-side injects ([mcap][7])
+
+    // tape
+    int tape_every = 0;
+    std::vector<st::TapeStep> tape;
+    std::vector<st::Snapshot> snaps;  // one per tape_every steps
+
+    // coupled run
+    void *fieldbuf[2] = {};
+    hipStream_t side = nullptr;
+
+    std::string err;
+};
+
+namespace st {
+
+// Kernel launchers (st_kernels.hip).  All enqueue on `s`.
+hipError_t launch_items(st_ctx *c, hipStream_t s);
+hipError_t launch_reset(st_ctx *c, int force, hipStream_t s);
+hipError_t launch_flush_pending(st_ctx *c, hipStream_t s);
+hipError_t launch_zero_sources(st_ctx *c, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_step(st_ctx *c, const void *u, double dt, int record_moves, hipStream_t s);
+hipError_t launch_rebin(st_ctx *c, int force_full, hipStream_t s);
+hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,
+                               const double *d, int64_t at, hipStream_t s);
+hipError_t launch_get_particles(st_ctx *c, double *x, double *up, double *d, int64_t *id,
+                                int32_t *cell, hipStream_t s);
+hipError_t launch_get_sources(st_ctx *c, double *out, int reset, hipStream_t s);
+hipError_t launch_init_views(st_ctx *c, hipStream_t s);
+hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, double sn,
+                               hipStream_t s);
+hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s);
+size_t snapshot_bytes(const st_ctx *c);
+hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s);
+
+}  // namespace st

@@ -1,0 +1,1098 @@
+// HIP kernels of the scaletrack library, written for CDNA4 (gfx950, wave64).
+//
+// One step of the particle method (paper Sec. 2.1 equations of motion and
+// momentum source, Sec. 2.5 interpolation, deposit and time integration)
+// runs as:
+//   step      one workgroup per work item (a run of at most kSeg particles of
+//             one chunk): stage the chunk's fluid tile with a one-cell halo
+//             in LDS, gather, integrate, deposit into an LDS accumulator of
+//             the chunk's cells, write stayers in place, compact chunk
+//             crossers ("movers") with a wave ballot into a mover list, and
+//             flush the accumulator with one read-modify-write (or one
+//             atomic, for chunks split over several items) per cell;
+//   check     per chunk: new count, room check, arrival offsets (scan);
+//   inbox     movers grouped by destination chunk;
+//   fill      per chunk: arrivals and, when the chunk shrank, its tail
+//             particles fill the vacated slots, keeping the chunk dense;
+//   rekey     only when a chunk ran out of room, the mover list overflowed
+//             or particles were injected: full counting-sort re-bin into the
+//             other store (decided on the device, no host round trip).
+#include "st_internal.h"
+
+#include <math.h>
+
+namespace st {
+namespace {
+
+constexpr int kScanBlock = 1024;  // elements per block of the device scans
+
+__device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Exclusive prefix over the lanes of the wave that are set in `mask`.
+__device__ __forceinline__ int lanes_below(uint64_t mask)
+{
+    return __popcll(mask & ((1ull << lane_id()) - 1ull));
+}
+
+template <class V>
+__device__ V block_excl_scan(V v, V *sh, V &total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        V add = (t >= off) ? sh[t - off] : V(0);
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[blockDim.x - 1];
+    V excl = sh[t] - v;
+    __syncthreads();
+    return excl;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan: out[i] = sum_{j<i} in[i], out[n] = total.
+// `gate`, when non-null, must be non-zero for the scan to run.
+// ---------------------------------------------------------------------------
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_scan_partials(const TI *in, int64_t n, TO *part,
+                                                       const int32_t *gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ TO sh[256];
+    int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    TO s = 0;
+    for (int k = 0; k < kScanBlock / 256; ++k) {
+        int64_t i = b0 + k * 256 + threadIdx.x;
+        if (i < n) s += (TO)in[i];
+    }
+    TO tot;
+    block_excl_scan<TO>(s, sh, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+template <class TO>
+__global__ void __launch_bounds__(256) k_scan_spine(TO *part, int64_t nb, const int32_t *gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ TO sh[256];
+    TO carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        int64_t i = b0 + threadIdx.x;
+        TO v = i < nb ? part[i] : TO(0);
+        TO tot;
+        TO ex = block_excl_scan<TO>(v, sh, tot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_scan_final(const TI *in, int64_t n, const TO *part,
+                                                    TO *out, const int32_t *gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ TO sh[256];
+    int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    constexpr int K = kScanBlock / 256;
+    TO v[K];
+    TO s = 0;
+    // each thread owns K consecutive elements
+    for (int k = 0; k < K; ++k) {
+        int64_t i = b0 + (int64_t)threadIdx.x * K + k;
+        v[k] = i < n ? (TO)in[i] : TO(0);
+        s += v[k];
+    }
+    TO tot;
+    TO ex = block_excl_scan<TO>(s, sh, tot) + part[blockIdx.x];
+    for (int k = 0; k < K; ++k) {
+        int64_t i = b0 + (int64_t)threadIdx.x * K + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+        if (i == n - 1) out[n] = ex;
+    }
+}
+
+template <class TI, class TO>
+hipError_t scan_excl(const TI *in, TO *out, int64_t n, TO *part, const int32_t *gate,
+                     hipStream_t s)
+{
+    int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_scan_partials<TI, TO>), dim3(nb), dim3(256), 0, s, in, n, part, gate);
+    hipLaunchKernelGGL((k_scan_spine<TO>), dim3(1), dim3(256), 0, s, part, nb, gate);
+    hipLaunchKernelGGL((k_scan_final<TI, TO>), dim3(nb), dim3(256), 0, s, in, n, part, out,
+                       gate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small utilities
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template <class A>
+__global__ void k_fill_acc(A *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = A(0);
+}
+
+// chunk of (chunk coords) and back
+__device__ __forceinline__ int64_t chunk_index(const Params &p, int64_t cx, int64_t cy,
+                                               int64_t cz)
+{
+    return (cz * p.nc[1] + cy) * p.nc[0] + cx;
+}
+
+// Re-bin of a chunk-local offset that may have left [0, E): returns the
+// chunk shift along the axis and the offset relative to the new chunk.  A
+// rounding that lands exactly on E belongs to the next chunk at offset 0.
+template <class T>
+__device__ __forceinline__ int rebase(T &xi, int E)
+{
+    const T fe = T(E);
+    T kf = floor(xi / fe);
+    int k = (int)kf;
+    xi = xi - kf * fe;
+    if (xi < T(0)) { xi += fe; --k; }
+    if (xi >= fe) { xi -= fe; ++k; }
+    return k;
+}
+
+template <class T>
+__device__ __forceinline__ int64_t chunk_after(const Params &p, int64_t c, T &ox, T &oy, T &oz)
+{
+    int64_t cx = c % p.nc[0];
+    int64_t cy = (c / p.nc[0]) % p.nc[1];
+    int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
+    int kx = rebase(ox, p.E), ky = rebase(oy, p.E), kz = rebase(oz, p.E);
+    if ((kx | ky | kz) == 0) return c;
+    return chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
+                       wrapi(cz + kz, p.nc[2]));
+}
+
+// ---------------------------------------------------------------------------
+// work items: one per run of <= kSeg particles of a chunk
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_nseg(const View<T> *views, const int32_t *cur, int64_t C, int32_t *nseg)
+{
+    const int32_t *cnt = views[*cur].cnt;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x)
+        nseg[c] = (cnt[c] + kSeg - 1) / kSeg;
+}
+
+__global__ void k_items(const int32_t *nseg_excl, int64_t C, int32_t *items, int32_t *nitems)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int32_t o = nseg_excl[c], e = nseg_excl[c + 1];
+        for (int32_t s = 0; s < e - o; ++s) {
+            items[2 * (int64_t)(o + s)] = (int32_t)c;
+            items[2 * (int64_t)(o + s) + 1] = s;
+        }
+        if (c == C - 1) *nitems = e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the step kernel
+// ---------------------------------------------------------------------------
+template <class T, class A>
+struct StepArgs {
+    const View<T> *views;
+    const int32_t *cur;
+    const int32_t *items;
+    const int32_t *nitems;
+    const T *u;              // field [3][n2][n1][n0]
+    A *src;                  // [C][3][E^3]
+    Movers<T> mv;
+    int32_t *nmov;
+    int64_t mcap;
+    int32_t *out_cnt;
+    int32_t *in_cnt;
+    int32_t *hole;
+    int32_t *overflow;
+    int64_t grid;            // launched workgroups (for the XCD remap)
+    int32_t record;          // write movers (0 only for the tape recompute's dry runs)
+    Params p;
+    T dt;
+    T dt_h[3];               // dt / h per axis
+    T tau_coef;
+    T g[3];
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
+// XCD walks a contiguous range of work items (neighbouring chunks share
+// their halo cells through that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t grid)
+{
+    const int64_t nx = 8;
+    int64_t per = grid / nx;
+    int64_t rem = grid % nx;
+    int64_t x = bid % nx;
+    int64_t k = bid / nx;
+    // XCD x owns logical items [start_x, start_x + per + (x < rem))
+    int64_t start = x * per + (x < rem ? x : rem);
+    return start + k;
+}
+
+template <class T, class A, int E, int INTERP>
+__global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
+{
+    constexpr int S = E + 2;            // tile edge with the halo
+    constexpr int S3 = S * S * S;
+    constexpr int E3 = E * E * E;
+    __shared__ T tile[3 * S3];
+    __shared__ A acc[3 * E3];
+
+    const int64_t item = xcd_remap(blockIdx.x, a.grid);
+    if (item >= *a.nitems) return;
+    const View<T> V = a.views[*a.cur];
+    const int64_t c = a.items[2 * item];
+    const int64_t seg = a.items[2 * item + 1];
+    const int64_t base = V.base[c];
+    const int32_t cnt = V.cnt[c];
+    const int64_t s0 = base + seg * kSeg;
+    const int64_t s1 = min(s0 + (int64_t)kSeg, base + (int64_t)cnt);
+    const bool multi = cnt > kSeg;
+    const Params &p = a.p;
+    const int64_t cx = c % p.nc[0];
+    const int64_t cy = (c / p.nc[0]) % p.nc[1];
+    const int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
+    const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
+
+    // stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped
+    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
+        int comp = t / S3;
+        int r = t - comp * S3;
+        int k = r / (S * S);
+        int j = (r / S) % S;
+        int i = r % S;
+        int64_t gx = wrapi(cx * E - 1 + i, p.n[0]);
+        int64_t gy = wrapi(cy * E - 1 + j, p.n[1]);
+        int64_t gz = wrapi(cz * E - 1 + k, p.n[2]);
+        tile[t] = a.u[comp * ncell + (gz * p.n[1] + gy) * p.n[0] + gx];
+    }
+    for (int t = threadIdx.x; t < 3 * E3; t += kBlock) acc[t] = A(0);
+    __syncthreads();
+
+    const T dt = a.dt;
+    const A inv_V = (A)p.inv_V;
+    for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock) {
+        T xi[3] = {V.ox[q], V.oy[q], V.oz[q]};
+        T up[3] = {V.vx[q], V.vy[q], V.vz[q]};
+        const T dp = V.d[q];
+
+        // gather the fluid velocity at the particle
+        T uf[3];
+        int cl[3];
+        if (INTERP == 0) {
+            T f[3];
+            int i0[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                T s = xi[ax] - T(0.5);
+                T fl = floor(s);
+                // -1 .. E-1 for offsets in [0, E); clamped so that no state
+                // can index outside the tile
+                i0[ax] = min(max((int)fl, -1), E - 1);
+                f[ax] = s - fl;
+                cl[ax] = min(max((int)xi[ax], 0), E - 1);
+            }
+            const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
+            const T wx0 = T(1) - f[0], wx1 = f[0];
+            const T wy0 = T(1) - f[1], wy1 = f[1];
+            const T wz0 = T(1) - f[2], wz1 = f[2];
+            const T w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+            for (int comp = 0; comp < 3; ++comp) {
+                const T *tc = tile + comp * S3 + t0;
+                T r00 = wx0 * tc[0] + wx1 * tc[1];
+                T r10 = wx0 * tc[S] + wx1 * tc[S + 1];
+                T r01 = wx0 * tc[S * S] + wx1 * tc[S * S + 1];
+                T r11 = wx0 * tc[S * S + S] + wx1 * tc[S * S + S + 1];
+                uf[comp] = w00 * r00 + w10 * r10 + w01 * r01 + w11 * r11;
+            }
+        } else {
+            for (int ax = 0; ax < 3; ++ax) cl[ax] = min(max((int)xi[ax], 0), E - 1);
+            const int t0 = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
+            for (int comp = 0; comp < 3; ++comp) uf[comp] = tile[comp * S3 + t0];
+        }
+
+        // semi-implicit Euler, drag implicit and gravity explicit:
+        //   u_p' = (tau u_p + dt u_f + tau dt g) / (tau + dt)
+        // written as the velocity change, which keeps its relative accuracy
+        // in binary32:  u_p' - u_p = dt (u_f - u_p + tau g) / (tau + dt)
+        const T tau = a.tau_coef * dp * dp;
+        const T rD = dt / (tau + dt);
+        T upn[3], xn[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            upn[ax] = up[ax] + rD * ((uf[ax] - up[ax]) + tau * a.g[ax]);
+            xn[ax] = xi[ax] + upn[ax] * a.dt_h[ax];
+        }
+
+        // drag impulse J = m (u_p' - u_p - g dt) = m dt (u_f - u_p - g dt) / (tau + dt),
+        // evaluated in the accumulator precision from the stored inputs
+        const A dA = (A)dp;
+        const A mass = (A)p.mass_coef * dA * dA * dA;
+        const A tauA = (A)p.tau_coef * dA * dA;
+        const A dtA = (A)dt;
+        const A coef = -mass * dtA / (tauA + dtA) * inv_V;   // -(m dt / (tau+dt)) / V
+        const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+        for (int ax = 0; ax < 3; ++ax) {
+            A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
+            atomicAdd(&acc[ax * E3 + cell], coef * slip);
+        }
+
+        // relocate
+        T xr[3] = {xn[0], xn[1], xn[2]};
+        const int64_t cn = chunk_after(p, c, xr[0], xr[1], xr[2]);
+        const bool mover = cn != c;
+        V.vx[q] = upn[0];
+        V.vy[q] = upn[1];
+        V.vz[q] = upn[2];
+        // stayers keep their re-based offsets; movers keep the un-rebased
+        // ones (relative to this chunk) so that a full re-bin can re-key them
+        V.ox[q] = mover ? xn[0] : xr[0];
+        V.oy[q] = mover ? xn[1] : xr[1];
+        V.oz[q] = mover ? xn[2] : xr[2];
+
+        const uint64_t mask = __ballot(mover);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            const int nw = __popcll(mask);
+            const int below = lanes_below(mask);
+            int32_t mbase = 0, hbase = 0;
+            if (lane_id() == leader) {
+                mbase = atomicAdd(a.nmov, nw);
+                hbase = atomicAdd(&a.out_cnt[c], nw);
+            }
+            mbase = __shfl(mbase, leader);
+            hbase = __shfl(hbase, leader);
+            if (mover) {
+                const int32_t id = V.id[q];
+                V.id[q] = -1 - id;
+                a.hole[base + hbase + below] = (int32_t)(q - base);
+                const int64_t m = (int64_t)mbase + below;
+                if (a.record && m < a.mcap) {
+                    a.mv.ox[m] = xr[0];
+                    a.mv.oy[m] = xr[1];
+                    a.mv.oz[m] = xr[2];
+                    a.mv.vx[m] = upn[0];
+                    a.mv.vy[m] = upn[1];
+                    a.mv.vz[m] = upn[2];
+                    a.mv.d[m] = dp;
+                    a.mv.id[m] = id;
+                    a.mv.dest[m] = (int32_t)cn;
+                    a.mv.rank[m] = atomicAdd(&a.in_cnt[cn], 1);
+                } else {
+                    *a.overflow = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // flush the chunk's accumulated source
+    A *dst = a.src + c * (3 * E3);
+    for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
+        A v = acc[t];
+        if (v != A(0)) {
+            if (multi) atomicAdd(dst + t, v);
+            else dst[t] += v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// mover-only re-bin
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_check(const View<T> *views, const int32_t *cur, int64_t C,
+                        const int32_t *out_cnt, const int32_t *in_cnt, const int32_t *nmov,
+                        int64_t mcap, int32_t *flags)
+{
+    const View<T> V = views[*cur];
+    int bad = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t nc = (int64_t)V.cnt[c] - out_cnt[c] + in_cnt[c];
+        if (nc > V.room[c]) bad = 1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && *nmov > mcap) bad = 1;
+    if (bad) flags[F_OVERFLOW] = 1;
+}
+
+template <class T>
+__global__ void k_inbox(const Movers<T> mv, const int32_t *nmov, int64_t mcap,
+                        const int32_t *in_off, int32_t *inbox, const int32_t *flags)
+{
+    if (flags[F_OVERFLOW] | flags[F_FORCE]) return;
+    const int64_t n = min((int64_t)*nmov, mcap);
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
+         m += (int64_t)gridDim.x * blockDim.x)
+        inbox[in_off[mv.dest[m]] + mv.rank[m]] = (int32_t)m;
+}
+
+template <class T>
+__device__ __forceinline__ void copy_slot(const View<T> &V, int64_t dst, int64_t src)
+{
+    V.ox[dst] = V.ox[src];
+    V.oy[dst] = V.oy[src];
+    V.oz[dst] = V.oz[src];
+    V.vx[dst] = V.vx[src];
+    V.vy[dst] = V.vy[src];
+    V.vz[dst] = V.vz[src];
+    V.d[dst] = V.d[src];
+    V.id[dst] = V.id[src];
+}
+
+template <class T>
+__device__ __forceinline__ void place_mover(const View<T> &V, int64_t dst, const Movers<T> &mv,
+                                            int64_t m)
+{
+    V.ox[dst] = mv.ox[m];
+    V.oy[dst] = mv.oy[m];
+    V.oz[dst] = mv.oz[m];
+    V.vx[dst] = mv.vx[m];
+    V.vy[dst] = mv.vy[m];
+    V.vz[dst] = mv.vz[m];
+    V.d[dst] = mv.d[m];
+    V.id[dst] = mv.id[m];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_fill(const View<T> *views, const int32_t *cur, int64_t C,
+                                              const int32_t *out_cnt, const int32_t *in_cnt,
+                                              const int32_t *in_off, const int32_t *inbox,
+                                              const Movers<T> mv, int32_t *hole,
+                                              const int32_t *flags)
+{
+    if (flags[F_OVERFLOW] | flags[F_FORCE]) return;
+    __shared__ int32_t sh[256];
+    const View<T> V = views[*cur];
+    for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const int32_t out = out_cnt[c], in = in_cnt[c];
+        if (out == 0 && in == 0) continue;
+        const int64_t base = V.base[c];
+        const int32_t cnt = V.cnt[c];
+        const int32_t ncnt = cnt - out + in;
+        int32_t *H = hole + base;            // chunk-relative vacated slots
+        const int32_t *box = inbox + in_off[c];
+        if (ncnt >= cnt) {
+            // every vacated slot lies below the new count: arrivals fill
+            // them first, then extend the chunk
+            for (int32_t r = threadIdx.x; r < in; r += blockDim.x) {
+                int64_t dst = base + (r < out ? H[r] : cnt + (r - out));
+                place_mover(V, dst, mv, box[r]);
+            }
+        } else {
+            // keep the vacated slots below the new count (in place)
+            int32_t k = 0;
+            for (int32_t j0 = 0; j0 < out; j0 += blockDim.x) {
+                int32_t j = j0 + threadIdx.x;
+                int32_t h = j < out ? H[j] : 0;
+                int32_t keep = (j < out && h < ncnt) ? 1 : 0;
+                int32_t tot;
+                int32_t ex = block_excl_scan<int32_t>(keep, sh, tot);
+                if (keep) H[k + ex] = h;
+                k += tot;
+                __syncthreads();
+            }
+            // arrivals take the first `in` of them
+            for (int32_t r = threadIdx.x; r < in; r += blockDim.x)
+                place_mover(V, base + H[r], mv, box[r]);
+            // live particles beyond the new count take the rest
+            int32_t placed = 0;
+            const int32_t tail = cnt - ncnt;
+            for (int32_t t0 = 0; t0 < tail; t0 += blockDim.x) {
+                int32_t t = t0 + threadIdx.x;
+                int64_t slot = base + ncnt + t;
+                int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
+                int32_t tot;
+                int32_t ex = block_excl_scan<int32_t>(live, sh, tot);
+                if (live) copy_slot(V, base + H[in + placed + ex], slot);
+                placed += tot;
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) V.cnt[c] = ncnt;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// full re-bin (counting sort into the other store)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_rekey_count(const View<T> *views, const int32_t *cur,
+                                                     const int32_t *items, const int32_t *nitems,
+                                                     Params p, const Movers<T> mv, int64_t npend,
+                                                     int32_t *new_cnt, const int32_t *flags)
+{
+    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
+    const View<T> V = views[*cur];
+    const int64_t ni = *nitems;
+    for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
+        const int64_t c = items[2 * it], seg = items[2 * it + 1];
+        const int64_t s0 = V.base[c] + seg * kSeg;
+        const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
+        for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+            T x = V.ox[q], y = V.oy[q], z = V.oz[q];
+            int64_t cn = chunk_after(p, c, x, y, z);
+            atomicAdd(&new_cnt[cn], 1);
+        }
+    }
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
+         m += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&new_cnt[mv.dest[m]], 1);
+}
+
+__global__ void k_rooms(const int32_t *new_cnt, int64_t C, int64_t slots, int64_t total,
+                        int32_t *room_out, const int32_t *flags)
+{
+    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
+    // spare slots shared out in proportion to (count + kSlackMin)
+    const int64_t spare = slots - total;
+    const int64_t denom = total + (int64_t)kSlackMin * C;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = new_cnt[c];
+        int64_t extra = denom > 0 ? (spare * (n + kSlackMin)) / denom : 0;
+        room_out[c] = (int32_t)(n + extra);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_rekey_scatter(const View<T> *views, const int32_t *cur,
+                                                       const int32_t *items, const int32_t *nitems,
+                                                       Params p, const Movers<T> mv, int64_t npend,
+                                                       const int64_t *nbase, int32_t *cursor,
+                                                       const int32_t *flags)
+{
+    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
+    const View<T> V = views[*cur];
+    const View<T> W = views[1 - *cur];
+    const int64_t ni = *nitems;
+    for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
+        const int64_t c = items[2 * it], seg = items[2 * it + 1];
+        const int64_t s0 = V.base[c] + seg * kSeg;
+        const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
+        for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+            T x = V.ox[q], y = V.oy[q], z = V.oz[q];
+            int64_t cn = chunk_after(p, c, x, y, z);
+            int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+            W.ox[dst] = x;
+            W.oy[dst] = y;
+            W.oz[dst] = z;
+            W.vx[dst] = V.vx[q];
+            W.vy[dst] = V.vy[q];
+            W.vz[dst] = V.vz[q];
+            W.d[dst] = V.d[q];
+            int32_t id = V.id[q];
+            W.id[dst] = id < 0 ? -1 - id : id;
+        }
+    }
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        int64_t cn = mv.dest[m];
+        int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+        W.ox[dst] = mv.ox[m];
+        W.oy[dst] = mv.oy[m];
+        W.oz[dst] = mv.oz[m];
+        W.vx[dst] = mv.vx[m];
+        W.vy[dst] = mv.vy[m];
+        W.vz[dst] = mv.vz[m];
+        W.d[dst] = mv.d[m];
+        W.id[dst] = mv.id[m];
+    }
+}
+
+template <class T>
+__global__ void k_rekey_finish(const View<T> *views, const int32_t *cur, int64_t C,
+                               const int32_t *new_cnt, const int64_t *nbase,
+                               const int32_t *nroom, const int32_t *flags)
+{
+    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
+    const View<T> W = views[1 - *cur];
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        W.cnt[c] = new_cnt[c];
+        W.base[c] = nbase[c];
+        W.room[c] = nroom[c];
+    }
+}
+
+__global__ void k_flip(int32_t *cur, int32_t *flags)
+{
+    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
+    *cur = 1 - *cur;
+    flags[F_REPACKS] += 1;
+}
+
+// per-step reset of counters
+__global__ void k_reset(int64_t C, int32_t *out_cnt, int32_t *in_cnt, int32_t *new_cnt,
+                        int32_t *cursor, int32_t *flags, int32_t force)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        out_cnt[c] = 0;
+        in_cnt[c] = 0;
+        new_cnt[c] = 0;
+        cursor[c] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flags[F_OVERFLOW] = 0;
+        flags[F_NMOV] = 0;
+        flags[F_FORCE] = force;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// inject: binary64 global positions -> chunk + chunk-local offsets, staged
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_stage(int64_t n, const double *x, const double *up, const double *d,
+                        int64_t at, int64_t id0, Params p, Movers<T> mv, int32_t *flags)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        bool ok = true;
+        int64_t ch[3];
+        T loc[3];
+        for (int a = 0; a < 3; ++a) {
+            double xa = x[3 * i + a];
+            if (!isfinite(xa)) { ok = false; xa = 0.0; }
+            // periodic image in [0, L)
+            xa = xa - floor(xa / p.L[a]) * p.L[a];
+            if (xa >= p.L[a] || xa < 0.0) xa = 0.0;
+            double g = xa / p.h[a];                  // cell units
+            int64_t ci = (int64_t)floor(g);
+            if (ci >= p.n[a]) { g -= p.n[a]; ci -= p.n[a]; }
+            if (ci < 0) { g += p.n[a]; ci += p.n[a]; }
+            ch[a] = ci / p.E;
+            T o = (T)(g - (double)(ch[a] * p.E));   // exact before the rounding to T
+            int k = rebase(o, p.E);
+            ch[a] = wrapi(ch[a] + k, p.nc[a]);
+            loc[a] = o;
+        }
+        double v[3] = {up[3 * i], up[3 * i + 1], up[3 * i + 2]};
+        double dd = d[i];
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(v[a])) ok = false;
+        if (!isfinite(dd) || !(dd > 0.0)) ok = false;
+        const int64_t m = at + i;
+        mv.ox[m] = loc[0];
+        mv.oy[m] = loc[1];
+        mv.oz[m] = loc[2];
+        mv.vx[m] = (T)v[0];
+        mv.vy[m] = (T)v[1];
+        mv.vz[m] = (T)v[2];
+        mv.d[m] = (T)dd;
+        mv.id[m] = (int32_t)(id0 + i);
+        mv.dest[m] = (int32_t)chunk_index(p, ch[0], ch[1], ch[2]);
+        mv.rank[m] = 0;
+        if (!ok) flags[F_BADINPUT] = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// outputs
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_get_particles(const View<T> *views, const int32_t *cur,
+                                                       const int32_t *items, const int32_t *nitems,
+                                                       Params p, int64_t count, double *x,
+                                                       double *up, double *d, int64_t *id,
+                                                       int32_t *cell)
+{
+    const View<T> V = views[*cur];
+    const int64_t ni = *nitems;
+    for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
+        const int64_t c = items[2 * it], seg = items[2 * it + 1];
+        const int64_t cc[3] = {c % p.nc[0], (c / p.nc[0]) % p.nc[1],
+                               c / ((int64_t)p.nc[0] * p.nc[1])};
+        const int64_t s0 = V.base[c] + seg * kSeg;
+        const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
+        for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+            const int64_t k = V.id[q];
+            if (k < 0 || k >= count) continue;  // never in a consistent store
+            const T o[3] = {V.ox[q], V.oy[q], V.oz[q]};
+            const T v[3] = {V.vx[q], V.vy[q], V.vz[q]};
+            for (int a = 0; a < 3; ++a) {
+                const double org = (double)(cc[a] * p.E);
+                if (x) x[3 * k + a] = (org + (double)o[a]) * p.h[a];
+                if (up) up[3 * k + a] = (double)v[a];
+                if (cell) cell[3 * k + a] = (int32_t)(cc[a] * p.E + min(max((int)o[a], 0), p.E - 1));
+            }
+            if (d) d[k] = (double)V.d[q];
+            if (id) id[k] = k;
+        }
+    }
+}
+
+template <class A>
+__global__ void k_get_sources(A *src, Params p, double *out, int reset)
+{
+    const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int64_t ncell = nx * ny * nz;
+    const int E = p.E;
+    const int64_t E3 = (int64_t)E * E * E;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t comp = t / ncell;
+        const int64_t r = t - comp * ncell;
+        const int64_t i = r % nx, j = (r / nx) % ny, k = r / (nx * ny);
+        const int64_t c = ((k / E) * p.nc[1] + (j / E)) * p.nc[0] + (i / E);
+        const int64_t l = ((k % E) * E + (j % E)) * E + (i % E);
+        A *s = src + c * 3 * E3 + comp * E3 + l;
+        out[t] = (double)*s;
+        if (reset) *s = A(0);
+    }
+}
+
+// synthetic fluid update: U^k = R_z(theta_k) U^0, rounded once to T
+template <class T>
+__global__ void k_rotate(const T *u0, T *u, int64_t ncell, double cs, double sn)
+{
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ncell;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double ux = (double)u0[q], uy = (double)u0[ncell + q];
+        u[q] = (T)(cs * ux - sn * uy);
+        u[ncell + q] = (T)(sn * ux + cs * uy);
+        u[2 * ncell + q] = u0[2 * ncell + q];
+    }
+}
+
+// checkpoint copy of the current store (all slots) and its layout
+template <class T>
+__global__ void k_snapshot(const View<T> *views, const int32_t *cur, int64_t slots, int64_t C,
+                           char *buf, int restore)
+{
+    const View<T> V = views[*cur];
+    T *arr[7] = {V.ox, V.oy, V.oz, V.vx, V.vy, V.vz, V.d};
+    T *sT = reinterpret_cast<T *>(buf);
+    int32_t *sid = reinterpret_cast<int32_t *>(sT + 7 * slots);
+    int64_t *sbase = reinterpret_cast<int64_t *>(
+        buf + (((7 * slots * sizeof(T) + slots * 4) + 7) & ~(size_t)7));
+    int32_t *sroom = reinterpret_cast<int32_t *>(sbase + C);
+    int32_t *scnt = sroom + C;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = g0; q < slots; q += gs) {
+        if (restore) {
+            for (int a = 0; a < 7; ++a) arr[a][q] = sT[a * slots + q];
+            V.id[q] = sid[q];
+        } else {
+            for (int a = 0; a < 7; ++a) sT[a * slots + q] = arr[a][q];
+            sid[q] = V.id[q];
+        }
+    }
+    for (int64_t c = g0; c < C; c += gs) {
+        if (restore) {
+            V.base[c] = sbase[c];
+            V.room[c] = sroom[c];
+            V.cnt[c] = scnt[c];
+        } else {
+            sbase[c] = V.base[c];
+            sroom[c] = V.room[c];
+            scnt[c] = V.cnt[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side helpers
+// ---------------------------------------------------------------------------
+inline int64_t grid_for(int64_t n, int64_t cap = 8192)
+{
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    return g > cap ? cap : g;
+}
+
+template <class T>
+Movers<T> movers_of(st_ctx *c)
+{
+    Movers<T> m;
+    m.ox = (T *)c->mov[0];
+    m.oy = (T *)c->mov[1];
+    m.oz = (T *)c->mov[2];
+    m.vx = (T *)c->mov[3];
+    m.vy = (T *)c->mov[4];
+    m.vz = (T *)c->mov[5];
+    m.d = (T *)c->mov[6];
+    m.id = (int32_t *)c->mov[7];
+    m.dest = (int32_t *)c->mov[8];
+    m.rank = (int32_t *)c->mov[9];
+    return m;
+}
+
+template <class F>
+hipError_t dispatch(st_ctx *c, F &&f)
+{
+    switch (c->form) {
+    case ST_FORM_FP64: return f(double(0), double(0));
+    case ST_FORM_FP32_LOCAL: return f(float(0), double(0));
+    default: return f(float(0), float(0));
+    }
+}
+
+template <class T, class A, int E, int I>
+hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step<T, A, E, I>), dim3(c->max_items), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class T, class A, int E>
+hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+{
+    return c->prm.interp == 1 ? launch_step_t<T, A, E, 1>(c, a, s)
+                              : launch_step_t<T, A, E, 0>(c, a, s);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_init_views(st_ctx *c, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        View<T> v[2];
+        for (int b = 0; b < 2; ++b) {
+            v[b].ox = (T *)c->store[b][0];
+            v[b].oy = (T *)c->store[b][1];
+            v[b].oz = (T *)c->store[b][2];
+            v[b].vx = (T *)c->store[b][3];
+            v[b].vy = (T *)c->store[b][4];
+            v[b].vz = (T *)c->store[b][5];
+            v[b].d = (T *)c->store[b][6];
+            v[b].id = (int32_t *)c->store[b][7];
+            v[b].base = c->base[b];
+            v[b].room = c->room[b];
+            v[b].cnt = c->cnt[b];
+        }
+        hipError_t e = hipMemcpyAsync(c->views, v, sizeof v, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    });
+}
+
+hipError_t launch_items(st_ctx *c, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        const View<T> *views = (const View<T> *)c->views;
+        int32_t *nseg = c->nseg;
+        int32_t *noff = c->nseg + c->C + 1;
+        hipLaunchKernelGGL((k_nseg<T>), dim3(grid_for(c->C)), dim3(256), 0, s, views, c->cur,
+                           c->C, nseg);
+        hipError_t e = scan_excl<int32_t, int32_t>(nseg, noff, c->C, (int32_t *)c->scan_tmp,
+                                                   nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_items, dim3(grid_for(c->C)), dim3(256), 0, s, noff, c->C, c->items,
+                           c->flags + F_NITEMS);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_rebin(st_ctx *c, int force_full, hipStream_t s)
+{
+    (void)force_full;  // the force flag was set on the device by the reset
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        const View<T> *views = (const View<T> *)c->views;
+        const Movers<T> mv = movers_of<T>(c);
+        const int64_t C = c->C;
+        hipLaunchKernelGGL((k_check<T>), dim3(grid_for(C)), dim3(256), 0, s, views, c->cur, C,
+                           c->out_cnt, c->in_cnt, c->flags + F_NMOV, c->mcap, c->flags);
+        hipError_t e = scan_excl<int32_t, int32_t>(c->in_cnt, c->in_off, C,
+                                                   (int32_t *)c->scan_tmp, nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_inbox<T>), dim3(grid_for(c->mcap)), dim3(256), 0, s, mv,
+                           c->flags + F_NMOV, c->mcap, c->in_off, c->inbox, c->flags);
+        int64_t gf = C < 65536 ? C : 65536;
+        hipLaunchKernelGGL((k_fill<T>), dim3(gf), dim3(256), 0, s, views, c->cur, C, c->out_cnt,
+                           c->in_cnt, c->in_off, c->inbox, mv, c->hole, c->flags);
+        // full re-bin, gated on the device by the overflow / force flags
+        const int64_t total = c->count + c->pending;
+        int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
+        hipLaunchKernelGGL((k_rekey_count<T>), dim3(gi), dim3(256), 0, s, views, c->cur, c->items,
+                           c->flags + F_NITEMS, c->prm, mv, c->pending, c->new_cnt, c->flags);
+        hipLaunchKernelGGL(k_rooms, dim3(grid_for(C)), dim3(256), 0, s, c->new_cnt, C, c->slots,
+                           total, c->nroom, c->flags);
+        e = scan_excl<int32_t, int64_t>(c->nroom, c->nbase, C, c->scan_tmp, nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gi), dim3(256), 0, s, views, c->cur,
+                           c->items, c->flags + F_NITEMS, c->prm, mv, c->pending, c->nbase,
+                           c->cursor, c->flags);
+        hipLaunchKernelGGL((k_rekey_finish<T>), dim3(grid_for(C)), dim3(256), 0, s, views, c->cur,
+                           C, c->new_cnt, c->nbase, c->nroom, c->flags);
+        hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, c->cur, c->flags);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_items(c, s);
+    });
+}
+
+hipError_t launch_reset(st_ctx *c, int force, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset, dim3(grid_for(c->C)), dim3(256), 0, s, c->C, c->out_cnt,
+                       c->in_cnt, c->new_cnt, c->cursor, c->flags, force);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(st_ctx *c, const void *u, double dt, int record, hipStream_t s)
+{
+    hipError_t e = launch_reset(c, 0, s);
+    if (e != hipSuccess) return e;
+    e = dispatch(c, [&](auto t, auto acc) -> hipError_t {
+        using T = decltype(t);
+        using A = decltype(acc);
+        StepArgs<T, A> a;
+        a.views = (const View<T> *)c->views;
+        a.cur = c->cur;
+        a.items = c->items;
+        a.nitems = c->flags + F_NITEMS;
+        a.u = (const T *)u;
+        a.src = (A *)c->src;
+        a.mv = movers_of<T>(c);
+        a.nmov = c->flags + F_NMOV;
+        a.mcap = c->mcap;
+        a.out_cnt = c->out_cnt;
+        a.in_cnt = c->in_cnt;
+        a.hole = c->hole;
+        a.overflow = c->flags + F_OVERFLOW;
+        a.grid = c->max_items;
+        a.record = record;
+        a.p = c->prm;
+        a.dt = (T)dt;
+        for (int ax = 0; ax < 3; ++ax) {
+            a.dt_h[ax] = (T)(dt / c->prm.h[ax]);
+            a.g[ax] = (T)c->prm.g[ax];
+        }
+        a.tau_coef = (T)c->prm.tau_coef;
+        switch (c->prm.E) {
+        case 2: return launch_step_e<T, A, 2>(c, a, s);
+        case 4: return launch_step_e<T, A, 4>(c, a, s);
+        default: return launch_step_e<T, A, 8>(c, a, s);
+        }
+    });
+    if (e != hipSuccess) return e;
+    return launch_rebin(c, 0, s);
+}
+
+hipError_t launch_flush_pending(st_ctx *c, hipStream_t s)
+{
+    hipError_t e = launch_reset(c, 1, s);
+    if (e != hipSuccess) return e;
+    return launch_rebin(c, 1, s);
+}
+
+hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,
+                               const double *d, int64_t at, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        hipLaunchKernelGGL((k_stage<T>), dim3(grid_for(n)), dim3(256), 0, s, n, x, up, d, at,
+                           c->next_id, c->prm, movers_of<T>(c),
+                           c->flags);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_get_particles(st_ctx *c, double *x, double *up, double *d, int64_t *id,
+                                int32_t *cell, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
+        hipLaunchKernelGGL((k_get_particles<T>), dim3(gi), dim3(256), 0, s,
+                           (const View<T> *)c->views, c->cur, c->items, c->flags + F_NITEMS,
+                           c->prm, c->count, x, up, d, id, cell);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_get_sources(st_ctx *c, double *out, int reset, hipStream_t s)
+{
+    return dispatch(c, [&](auto, auto acc) -> hipError_t {
+        using A = decltype(acc);
+        int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        hipLaunchKernelGGL((k_get_sources<A>), dim3(grid_for(n)), dim3(256), 0, s, (A *)c->src,
+                           c->prm, out, reset);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_zero_sources(st_ctx *c, hipStream_t s)
+{
+    return dispatch(c, [&](auto, auto acc) -> hipError_t {
+        using A = decltype(acc);
+        int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        hipLaunchKernelGGL((k_fill_acc<A>), dim3(grid_for(n)), dim3(256), 0, s, (A *)c->src, n);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) { return fill_i32(p, n, 0, s); }
+
+hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, double sn,
+                               hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        int64_t ncell = (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        hipLaunchKernelGGL((k_rotate<T>), dim3(grid_for(ncell, 16384)), dim3(256), 0, s,
+                           (const T *)u0, (T *)out, ncell, cs, sn);
+        return hipGetLastError();
+    });
+}
+
+size_t snapshot_bytes(const st_ctx *c)
+{
+    size_t head = (7 * (size_t)c->slots * c->tsize + (size_t)c->slots * 4 + 7) & ~(size_t)7;
+    return head + (size_t)c->C * 16;
+}
+
+hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        hipLaunchKernelGGL((k_snapshot<T>), dim3(grid_for(c->slots)), dim3(256), 0, s,
+                           (const View<T> *)c->views, c->cur, c->slots, c->C, (char *)dst,
+                           restore);
+        return hipGetLastError();
+    });
+}
+
+}  // namespace st
+

@@ -1,0 +1,116 @@
+"""Shared pieces of the GPU parity tests: trackers built from a workload,
+the oracle stepped from the GPU's own state (lockstep), and comparisons
+that exclude, and count, particles within 1e-6 cell widths of a face."""
+import dataclasses
+import math
+
+import numpy as np
+
+from oracle.oracle import MeshParams, load as load_oracle
+from workloads import synth
+
+FORMS = ("fp64", "fp32_local", "fp32")
+BAND = 1e-6  # cell widths
+
+
+def workload(name="tg32", **kw):
+    w = synth.get(name)
+    return dataclasses.replace(w, **kw) if kw else w
+
+
+def oracle_mesh(w, interp=0):
+    return MeshParams(interp=interp, **w.mesh_kwargs())
+
+
+def tracker(w, form, capacity=None, interp="trilinear"):
+    import paper_2603_26691_amd as pkg
+    return pkg.Tracker(w.n, w.L, capacity or max(w.P, 1), form=form, interp=interp,
+                       chunk_edge=w.chunk_edge, rho_f=w.rho_f, mu_f=w.mu_f, g=w.g,
+                       rho_p=w.rho_p, parcel_weight=w.parcel_weight)
+
+
+def fields(w, form):
+    """(device field for the tracker, float64 field the oracle gets)."""
+    import torch
+    U = w.field()
+    if form == "fp64":
+        return torch.from_numpy(U).cuda(), U
+    U32 = U.astype(np.float32)
+    return torch.from_numpy(U32).cuda(), U32.astype(np.float64)
+
+
+def state(t):
+    s = t.particles()
+    return {k: v.cpu().numpy() for k, v in s.items()}
+
+
+def face_distance(x, h):
+    """Distance of each coordinate to the nearest cell face, in cell widths."""
+    q = x / h
+    f = q - np.floor(q)
+    return np.minimum(f, 1.0 - f)
+
+
+def min_image(dx, L):
+    L = np.asarray(L)
+    return dx - np.round(dx / L) * L
+
+
+def lockstep_check(t, orc, mesh, Udev, Uor, dt, nsteps, tol, nsub=1):
+    """Steps the tracker and, from the GPU's state at every step, the oracle.
+
+    tol: dict with keys pos (/L), vel (/1 m/s), src (per-cell, relative to the
+    largest cell).  Returns the worst errors and the counts of excluded
+    particles and cells."""
+    L = np.array(mesh.L)
+    h = mesh.h
+    worst = {"pos": 0.0, "vel": 0.0, "src": 0.0, "band_cells": 0, "band_src_cells": 0,
+             "compared": 0}
+    t.sources(reset=True)
+    s0 = state(t)
+    for _ in range(nsteps):
+        t.step(Udev, dt, nsub=nsub)
+        s1 = state(t)
+        Sg = t.sources(reset=True).cpu().numpy()
+        xo, uo, So = orc.run(mesh, Uor, s0["x"], s0["up"], s0["d"], dt, 1, nsub=nsub)
+        assert np.array_equal(s1["id"], np.arange(s1["id"].shape[0])), "ids are a permutation"
+        assert np.array_equal(s1["d"], s0["d"]), "diameters travel with their particles"
+        dpos = np.abs(min_image(s1["x"] - xo, L)) / L
+        dvel = np.abs(s1["up"] - uo)
+        worst["pos"] = max(worst["pos"], float(dpos.max()))
+        worst["vel"] = max(worst["vel"], float(dvel.max()))
+        # cells after the step: bit-exact away from the faces
+        co = orc.cells(mesh, xo)
+        near = (face_distance(xo, h) < BAND).any(axis=1)
+        mism = (co != s1["cell"]).any(axis=1)
+        assert not (mism & ~near).any(), \
+            f"cell mismatch away from faces: {np.argwhere(mism & ~near)[:5].ravel()}"
+        worst["band_cells"] += int(near.sum())
+        worst["compared"] += int((~near).sum())
+        # sources: a particle whose start-of-step cell differs between the
+        # two sides (only possible within the band) puts its impulse in
+        # different cells; those cells are left out and counted
+        c0o = orc.cells(mesh, s0["x"])
+        diff0 = (c0o != s0["cell"]).any(axis=1)
+        assert not (diff0 & ~(face_distance(s0["x"], h) < BAND).any(axis=1)).any()
+        keep = np.ones(Sg.shape[1:], dtype=bool)
+        for p in np.nonzero(diff0)[0]:
+            for c in (c0o[p], s0["cell"][p]):
+                keep[c[2], c[1], c[0]] = False
+        worst["band_src_cells"] += int((~keep).sum())
+        for comp in range(3):
+            ref = So[comp]
+            scale = np.abs(ref).max()
+            if scale == 0:
+                continue
+            err = np.abs(Sg[comp] - ref)[keep].max() / scale
+            worst["src"] = max(worst["src"], float(err))
+        s0 = s1
+    assert worst["pos"] <= tol["pos"], worst
+    assert worst["vel"] <= tol["vel"], worst
+    assert worst["src"] <= tol["src"], worst
+    return worst
+
+
+def sphere_mass(d, w=1.0, rho_p=1000.0):
+    return w * rho_p * math.pi * d ** 3 / 6.0

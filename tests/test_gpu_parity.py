@@ -1,0 +1,189 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Lockstep: at every step the oracle takes the GPU's state (promoted exactly
+to binary64) and the field the GPU used, advances one step, and the GPU's
+next state, cells and per-cell sources are compared with it.  Cells must be
+bit-exact except for particles within 1e-6 cell widths of a face (excluded
+and counted).  Tolerances: positions (per L) and velocities (per 1 m/s)
+1e-5 and per-cell sources 1e-6 of the largest cell for the FP32
+chunk-local form; near round-off for the FP64 form; the FP32-everywhere
+form (precision study) is held to 1e-4 on sources.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (FORMS, fields, lockstep_check, min_image, oracle_mesh, state, tracker,
+                         workload, face_distance, sphere_mass, BAND)
+from oracle.oracle import load as load_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {
+    "fp64": {"pos": 1e-13, "vel": 1e-12, "src": 1e-10},
+    "fp32_local": {"pos": 1e-5, "vel": 1e-5, "src": 1e-6},
+    "fp32": {"pos": 1e-5, "vel": 1e-5, "src": 1e-4},
+}
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return load_oracle()
+
+
+def _run_lockstep(orc, w, form, nsteps=4, interp=0, nsub=1, dt=None):
+    t = tracker(w, form, interp="ngp" if interp else "trilinear")
+    x, up, d = w.particles()
+    t.inject(x, up, d)
+    Udev, Uor = fields(w, form)
+    out = lockstep_check(t, orc, oracle_mesh(w, interp), Udev, Uor, dt or w.dt, nsteps,
+                         TOL[form], nsub=nsub)
+    print(form, w.name, out)
+    t.close()
+    return out
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_lockstep_tg32(orc, form):
+    # 32^3 mesh (64 chunks), 20000 droplets, Taylor-Green field with noise
+    w = workload("tg32", P=20000, noise=0.1)
+    _run_lockstep(orc, w, form, nsteps=4)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_ngp(orc, form):
+    w = workload("tg32", P=20000, noise=0.1)
+    _run_lockstep(orc, w, form, nsteps=3, interp=1)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_substeps(orc, form):
+    w = workload("tg32", P=10000, noise=0.1)
+    _run_lockstep(orc, w, form, nsteps=2, nsub=3, dt=3e-4)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_chunk_split_over_items(orc, form):
+    # 16^3 mesh = 8 chunks with 25000 droplets each: every chunk is split
+    # over two work items and deposits with atomics
+    w = workload("tg32", n=(16, 16, 16), P=200000, noise=0.1)
+    _run_lockstep(orc, w, form, nsteps=3)
+
+
+@pytest.mark.parametrize("edge", [2, 4])
+def test_lockstep_small_chunks(orc, edge):
+    w = workload("tg32", n=(8, 8, 16), L=(0.05, 0.05, 0.1), P=5000, noise=0.2, chunk_edge=edge)
+    _run_lockstep(orc, w, "fp64", nsteps=3)
+    _run_lockstep(orc, w, "fp32_local", nsteps=3)
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_non_cubic(orc, form):
+    w = workload("tg32", n=(32, 16, 8), L=(0.1, 0.04, 0.025), P=20000, noise=0.1,
+                 g=(1.0, -2.0, -9.81))
+    _run_lockstep(orc, w, form, nsteps=3)
+
+
+def test_lockstep_plume_ragged(orc):
+    # uneven occupancy: one plume, most chunks sparse, a ragged count
+    w = workload("plume256", n=(32, 32, 32), P=30011, plumes=1, plume_fraction=0.7)
+    _run_lockstep(orc, w, "fp32_local", nsteps=4)
+
+
+def test_free_run_tg32_fp64(orc):
+    """Config-0 workload in full (1e5 droplets, 100 steps of 1e-4 s), FP64 form."""
+    w = workload("tg32")
+    t = tracker(w, "fp64")
+    x, up, d = w.particles()
+    t.inject(x, up, d)
+    s0 = state(t)
+    Udev, U = fields(w, "fp64")
+    for _ in range(w.nsteps):
+        t.step(Udev, w.dt)
+    s1 = state(t)
+    Sg = t.sources().cpu().numpy()
+    mesh = oracle_mesh(w)
+    xo, uo, So = orc.run(mesh, U, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps)
+    L = np.array(w.L)
+    assert np.abs(min_image(s1["x"] - xo, L)).max() / L.max() < 1e-11
+    assert np.abs(s1["up"] - uo).max() < 1e-10
+    # global source per component, relative to the summed magnitude
+    m = sphere_mass(s0["d"])
+    scale = (m[:, None] * np.abs(uo - s0["up"])).sum(axis=0) / np.prod(w.h)
+    glob = np.abs(Sg.reshape(3, -1).sum(axis=1) - So.reshape(3, -1).sum(axis=1))
+    assert np.all(glob <= 1e-10 * scale), (glob, scale)
+    # cells, away from faces
+    near = (face_distance(xo, w.h) < BAND).any(axis=1)
+    co = orc.cells(mesh, xo)
+    assert np.array_equal(co[~near], s1["cell"][~near])
+    t.close()
+
+
+def test_free_run_fp32_local(orc):
+    """Same workload for 100 steps in the FP32 chunk-local form: state within 1e-5."""
+    w = workload("tg32", P=50000, noise=0.1)
+    t = tracker(w, "fp32_local")
+    x, up, d = w.particles()
+    t.inject(x, up, d)
+    s0 = state(t)
+    Udev, U = fields(w, "fp32_local")
+    for _ in range(w.nsteps):
+        t.step(Udev, w.dt)
+    s1 = state(t)
+    Sg = t.sources().cpu().numpy()
+    xo, uo, So = orc.run(oracle_mesh(w), U, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps)
+    L = np.array(w.L)
+    pos = np.abs(min_image(s1["x"] - xo, L)).max() / L.max()
+    vel = np.abs(s1["up"] - uo).max()
+    m = sphere_mass(s0["d"])
+    scale = (m[:, None] * np.abs(uo - s0["up"])).sum(axis=0) / np.prod(w.h)
+    glob = np.abs(Sg.reshape(3, -1).sum(axis=1) - So.reshape(3, -1).sum(axis=1)) / scale
+    print("free-run fp32_local", pos, vel, glob)
+    assert pos < 1e-5 and vel < 1e-5 and np.all(glob < 1e-6)
+    t.close()
+
+
+def test_conservation_fp64():
+    """Deposited source balances the particles' momentum change (and gravity) to 1e-12."""
+    w = workload("tg32", P=50000, noise=0.1, parcel_weight=7.0)
+    t = tracker(w, "fp64")
+    x, up, d = w.particles()
+    up = np.random.default_rng(5).normal(0, 0.3, size=up.shape)
+    t.inject(x, up, d)
+    s0 = state(t)
+    Udev, _ = fields(w, "fp64")
+    n = 10
+    for _ in range(n):
+        t.step(Udev, w.dt)
+    s1 = state(t)
+    S = t.sources().cpu().numpy()
+    m = sphere_mass(s0["d"], 7.0)
+    dP = (m[:, None] * (s1["up"] - s0["up"])).sum(axis=0)
+    scale = np.abs(m[:, None] * (s1["up"] - s0["up"])).sum(axis=0)
+    resid = S.reshape(3, -1).sum(axis=1) * np.prod(w.h) + dP - n * w.dt * np.array(w.g) * m.sum()
+    assert np.all(np.abs(resid) <= 1e-12 * scale), resid / scale
+    t.close()
+
+
+def test_rebin_invariants(orc):
+    """After many steps every id is present once, every particle sits in the
+    chunk of its cell, and the count is conserved."""
+    w = workload("plume256", n=(32, 32, 32), P=40000, plumes=2, plume_fraction=0.8, noise=0.3)
+    t = tracker(w, "fp32_local")
+    x, up, d = w.particles()
+    t.inject(x, up, d)
+    Udev, _ = fields(w, "fp32_local")
+    for k in range(30):
+        t.step(Udev, 2e-4)
+    s = state(t)
+    assert t.count() == w.P
+    assert np.array_equal(s["id"], np.arange(w.P))
+    assert np.all(s["cell"] >= 0) and np.all(s["cell"] < np.array(w.n))
+    q = np.floor(s["x"] / w.h).astype(np.int64) % np.array(w.n)
+    near = (face_distance(s["x"], w.h) < BAND).any(axis=1)
+    assert np.array_equal(q[~near], s["cell"][~near])
+    st = t.stats()
+    print("stats", st)
+    assert st["particles"] == w.P
+    t.close()

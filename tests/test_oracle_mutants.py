@@ -7,6 +7,7 @@ a mutant that indexes out of bounds cannot take the test run down.
 """
 import concurrent.futures as cf
 import os
+import shutil
 import subprocess
 import sys
 import tempfile
@@ -96,8 +97,6 @@ def _build_and_pin(name, old, new, tmp):
     lib = os.path.join(tmp, f"m{tag}.so")
     with open(csrc, "w") as f:
         f.write(mutated)
-    import shutil
-    shutil.copy(os.path.join(ROOT, "oracle", "st_oracle.h"), tmp)
     subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
                     csrc, "-o", lib, "-lm"], check=True, capture_output=True)
     r = subprocess.run([sys.executable, os.path.join(HERE, "oracle_pins.py"), lib],
@@ -106,8 +105,14 @@ def _build_and_pin(name, old, new, tmp):
     return name, r.returncode, out
 
 
+def _tmpdir_with_header(tmp):
+    shutil.copy(os.path.join(ROOT, "oracle", "st_oracle.h"), tmp)
+    return tmp
+
+
 def test_every_mutant_fails_a_pin():
     with tempfile.TemporaryDirectory() as tmp:
+        _tmpdir_with_header(tmp)
         with cf.ThreadPoolExecutor(max_workers=6) as ex:
             futs = [ex.submit(_build_and_pin, k, o, n, tmp) for k, (o, n) in MUTANTS.items()]
             results = [f.result() for f in futs]
@@ -121,5 +126,6 @@ def test_every_mutant_fails_a_pin():
 
 def test_unmutated_copy_passes():
     with tempfile.TemporaryDirectory() as tmp:
+        _tmpdir_with_header(tmp)
         name, rc, out = _build_and_pin("identity", "st_oracle.h", "st_oracle.h", tmp)
     assert rc == 0 and out == "ALL_PASSED", out
