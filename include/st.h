@@ -167,10 +167,20 @@ st_status st_run_coupled(st_ctx *ctx, const void *u0, const double *cs,
                          float *step_ms, float *total_ms, void *hip_stream);
 
 /* Counters of the last st_step (host memory): movers, full repacks so far,
- * particles, store slots.  Any pointer may be NULL.  Synchronises the
- * stream. */
+ * particles, store slots, work items (chunk runs of the step kernel).  Any
+ * pointer may be NULL.  Synchronises the stream. */
 st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
-                   int64_t *particles, int64_t *slots, void *hip_stream);
+                   int64_t *particles, int64_t *slots, int64_t *items,
+                   void *hip_stream);
+
+/* Device time of the step kernel (the per-particle gather, integrate,
+ * deposit and relocate) measured with HIP events recorded around each of its
+ * launches on the launch stream.  enable != 0 starts a measurement (clearing
+ * earlier ones); enable == 0 stops it.  kernel_ms and launches (host, may be
+ * NULL) receive the summed milliseconds and the number of launches measured
+ * so far; reading them synchronises the recorded events. */
+st_status st_timing(st_ctx *ctx, int32_t enable, double *kernel_ms,
+                    int64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -58,7 +58,8 @@ SIGNATURES = {
     "st_run_coupled": (_I, [_P, _P, _P, _I32, _D, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P]),
     "st_stats": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
-                      ctypes.POINTER(_I64), _P]),
+                      ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
+    "st_timing": (_I, [_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 
 _lib = None

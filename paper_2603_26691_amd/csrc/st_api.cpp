@@ -46,20 +46,18 @@ hipError_t dalloc(P **p, size_t bytes, size_t &total)
 
 void free_all(st_ctx *c)
 {
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 8; ++k) (void)hipFree(c->store[b][k]);
-        (void)hipFree(c->base[b]);
-        (void)hipFree(c->room[b]);
-        (void)hipFree(c->cnt[b]);
-    }
     for (int k = 0; k < 10; ++k) (void)hipFree(c->mov[k]);
-    void *singles[] = {c->views, c->cur, c->out_cnt, c->in_cnt, c->in_off, c->cursor,
+    void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->in_off, c->cursor,
                        c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
                        c->scan_tmp, c->flags, c->src, c->stage64, c->fieldbuf[0],
                        c->fieldbuf[1]};
     for (void *p : singles) (void)hipFree(p);
     for (auto &sn : c->snaps) (void)hipFree(sn.buf);
     c->snaps.clear();
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+    c->tev.clear();
     if (c->side) (void)hipStreamDestroy(c->side);
 }
 
@@ -160,14 +158,12 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     for (int b = 0; b < 2; ++b) {
         for (int k = 0; k < 7; ++k) A(&c->store[b][k], (size_t)c->slots * c->tsize);
         A(&c->store[b][7], (size_t)c->slots * 4);
-        A(&c->base[b], (size_t)(C + 1) * 8);
-        A(&c->room[b], (size_t)C * 4);
-        A(&c->cnt[b], (size_t)C * 4);
     }
+    A(&c->base, (size_t)(C + 1) * 8);
+    A(&c->room, (size_t)C * 4);
+    A(&c->cnt, (size_t)C * 4);
     for (int k = 0; k < 7; ++k) A(&c->mov[k], (size_t)c->mcap * c->tsize);
     for (int k = 7; k < 10; ++k) A(&c->mov[k], (size_t)c->mcap * 4);
-    A(&c->views, 512);
-    A(&c->cur, 4);
     A(&c->out_cnt, (size_t)C * 4);
     A(&c->in_cnt, (size_t)C * 4);
     A(&c->in_off, (size_t)(C + 1) * 4);
@@ -178,7 +174,7 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     A(&c->hole, (size_t)c->slots * 4);
     A(&c->inbox, (size_t)c->mcap * 4);
     A(&c->items, (size_t)c->max_items * 8);
-    A(&c->nseg, (size_t)(2 * C + 2) * 4);
+    A(&c->nseg, (size_t)(C + 1) * 4);
     A(&c->scan_tmp, (size_t)(C / 1024 + 4) * 8);
     A(&c->flags, (size_t)st::F_COUNT * 4);
     A(&c->src, (size_t)3 * ncell * c->asize);
@@ -186,17 +182,8 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
         return dev_bad(ST_ERR_OOM, "device allocation failed after " + std::to_string(total) +
                                        " bytes");
     hipStream_t s = nullptr;
-    e = hipMemset(c->cur, 0, 4);
-    if (e == hipSuccess) e = hipMemset(c->flags, 0, st::F_COUNT * 4);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-        e = hipMemset(c->base[b], 0, (size_t)(C + 1) * 8);
-        if (e == hipSuccess) e = hipMemset(c->room[b], 0, (size_t)C * 4);
-        if (e == hipSuccess) e = hipMemset(c->cnt[b], 0, (size_t)C * 4);
-    }
-    if (e == hipSuccess) e = st::launch_init_views(c, s);
+    e = st::launch_init(c, s);
     if (e == hipSuccess) e = st::launch_zero_sources(c, s);
-    if (e == hipSuccess) e = st::launch_reset(c, 0, s);
-    if (e == hipSuccess) e = st::launch_items(c, s);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return dev_bad(ST_ERR_DEVICE, hipGetErrorString(e));
     *out = c;
@@ -520,7 +507,7 @@ st_status st_run_coupled(st_ctx *c, const void *u0, const double *cs, int32_t ns
 }
 
 st_status st_stats(st_ctx *c, int64_t *last_movers, int64_t *repacks, int64_t *particles,
-                   int64_t *slots, void *hip_stream)
+                   int64_t *slots, int64_t *items, void *hip_stream)
 {
     if (!c) return ST_ERR_INVALID;
     ST_HIP(hipSetDevice(c->device));
@@ -528,10 +515,32 @@ st_status st_stats(st_ctx *c, int64_t *last_movers, int64_t *repacks, int64_t *p
     int32_t f[st::F_COUNT];
     ST_HIP(hipMemcpyAsync(f, c->flags, sizeof f, hipMemcpyDeviceToHost, s));
     ST_HIP(hipStreamSynchronize(s));
-    if (last_movers) *last_movers = f[st::F_NMOV];
+    if (last_movers) *last_movers = f[st::F_LASTMOV];
     if (repacks) *repacks = f[st::F_REPACKS];
     if (particles) *particles = c->count + c->pending;
     if (slots) *slots = c->slots;
+    if (items) *items = f[st::F_NITEMS];
+    return ST_OK;
+}
+
+st_status st_timing(st_ctx *c, int32_t enable, double *kernel_ms, int64_t *launches)
+{
+    if (!c) return ST_ERR_INVALID;
+    ST_HIP(hipSetDevice(c->device));
+    double sum = 0.0;
+    for (size_t k = 0; k + 1 < c->tev.size(); k += 2) {
+        ST_HIP(hipEventSynchronize(c->tev[k + 1]));
+        float ms = 0.f;
+        ST_HIP(hipEventElapsedTime(&ms, c->tev[k], c->tev[k + 1]));
+        sum += ms;
+    }
+    if (kernel_ms) *kernel_ms = sum;
+    if (launches) *launches = (int64_t)(c->tev.size() / 2);
+    if (enable) {
+        for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+        c->tev.clear();
+    }
+    c->timing = enable ? 1 : 0;
     return ST_OK;
 }
 

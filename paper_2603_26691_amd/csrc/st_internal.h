@@ -5,9 +5,9 @@
 // [base[c], base[c] + room[c]); its cnt[c] live particles sit densely at
 // the start of that range.  Positions are stored as chunk-local offsets in
 // cell units, xi in [0, E) per axis; the chunk origin is exact (the chunk
-// index times E cells).  Two such stores exist; which one is current is
-// held on the device (views[*cur]) so that a re-bin decided on the device
-// never needs the host.
+// index times E cells).  Kernels get the store's pointers as arguments (so
+// every access is a global-memory instruction); a full re-bin scatters into
+// a second store and copies back.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,7 +22,8 @@ namespace st {
 
 constexpr int kBlock = 256;       // threads per workgroup of the step kernels
 constexpr int kSeg = 16384;       // max particles per step work item
-constexpr int kSlackMin = 32;     // spare slots per chunk at least (capacity sizing)
+constexpr int kSlackMin = 32;     // spare-slot weight per chunk in the room formula
+constexpr int kMoverStage = 512;  // movers per workgroup staged in LDS
 
 template <class T>
 struct View {
@@ -62,7 +63,7 @@ struct Params {
 
 // Flags and counters on the device (one int32 each).
 enum DevFlag { F_OVERFLOW = 0, F_NMOV = 1, F_NITEMS = 2, F_FORCE = 3, F_BADINPUT = 4,
-               F_REPACKS = 5, F_COUNT = 8 };
+               F_REPACKS = 5, F_LASTMOV = 6, F_COUNT = 8 };
 
 struct TapeStep {
     const void *u;     // field of the step (borrowed)
@@ -93,12 +94,10 @@ struct st_ctx {
     int64_t next_id = 0;
 
     // device memory
-    void *store[2][8] = {};    // SoA arrays of both stores
-    int64_t *base[2] = {};
-    int32_t *room[2] = {};
-    int32_t *cnt[2] = {};
-    void *views = nullptr;     // View<T>[2]
-    int32_t *cur = nullptr;    // index of the current store
+    void *store[2][8] = {};    // SoA arrays: [0] the store, [1] re-bin target
+    int64_t *base = nullptr;   // [C+1] layout of the store
+    int32_t *room = nullptr;   // [C]
+    int32_t *cnt = nullptr;    // [C]
     void *mov[10] = {};        // Movers arrays
     int32_t *out_cnt = nullptr, *in_cnt = nullptr;
     int32_t *in_off = nullptr;     // [C+1]
@@ -109,11 +108,11 @@ struct st_ctx {
     int32_t *hole = nullptr;       // [slots]
     int32_t *inbox = nullptr;      // [mcap]
     int32_t *items = nullptr;      // [max_items][2]
-    int32_t *nseg = nullptr;       // [C+1]
+    int32_t *nseg = nullptr;       // [C+1] offsets of the work items per chunk
     int64_t *scan_tmp = nullptr;   // block partials of the scans
     int32_t *flags = nullptr;      // DevFlag counters
     void *src = nullptr;           // [C][3][E^3] accumulator (double or float)
-    double *stage64 = nullptr;     // staging for host-side injects ([mcap][7])
+    double *stage64 = nullptr;     // staging for host-side injects ([batch][7])
 
     // tape
     int tape_every = 0;
@@ -124,25 +123,27 @@ struct st_ctx {
     void *fieldbuf[2] = {};
     hipStream_t side = nullptr;
 
+    // step-kernel timing (events recorded around each launch)
+    int timing = 0;
+    std::vector<hipEvent_t> tev;   // pairs: start, stop
+
     std::string err;
 };
 
 namespace st {
 
 // Kernel launchers (st_kernels.hip).  All enqueue on `s`.
+hipError_t launch_init(st_ctx *c, hipStream_t s);
 hipError_t launch_items(st_ctx *c, hipStream_t s);
-hipError_t launch_reset(st_ctx *c, int force, hipStream_t s);
 hipError_t launch_flush_pending(st_ctx *c, hipStream_t s);
 hipError_t launch_zero_sources(st_ctx *c, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_step(st_ctx *c, const void *u, double dt, int record_moves, hipStream_t s);
-hipError_t launch_rebin(st_ctx *c, int force_full, hipStream_t s);
 hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,
                                const double *d, int64_t at, hipStream_t s);
 hipError_t launch_get_particles(st_ctx *c, double *x, double *up, double *d, int64_t *id,
                                 int32_t *cell, hipStream_t s);
 hipError_t launch_get_sources(st_ctx *c, double *out, int reset, hipStream_t s);
-hipError_t launch_init_views(st_ctx *c, hipStream_t s);
 hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, double sn,
                                hipStream_t s);
 hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s);

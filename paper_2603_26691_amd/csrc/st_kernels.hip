@@ -6,17 +6,19 @@
 //   step      one workgroup per work item (a run of at most kSeg particles of
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
-//             the chunk's cells, write stayers in place, compact chunk
-//             crossers ("movers") with a wave ballot into a mover list, and
-//             flush the accumulator with one read-modify-write (or one
-//             atomic, for chunks split over several items) per cell;
-//   check     per chunk: new count, room check, arrival offsets (scan);
+//             the chunk's cells, write every particle back in place, collect
+//             the chunk crossers ("movers") in LDS and emit them with one
+//             global reservation per workgroup, and flush the accumulator
+//             with one read-modify-write (or one atomic, for chunks split
+//             over several items) per cell;
+//   scan      arrival offsets per chunk, and the room check;
 //   inbox     movers grouped by destination chunk;
 //   fill      per chunk: arrivals and, when the chunk shrank, its tail
 //             particles fill the vacated slots, keeping the chunk dense;
 //   rekey     only when a chunk ran out of room, the mover list overflowed
-//             or particles were injected: full counting-sort re-bin into the
-//             other store (decided on the device, no host round trip).
+//             or particles were injected: a full counting-sort re-bin into
+//             the second store, copied back (decided on the device);
+//   items     work items of the next step, and the reset of the counters.
 #include "st_internal.h"
 
 #include <math.h>
@@ -24,20 +26,22 @@
 namespace st {
 namespace {
 
-constexpr int kScanBlock = 1024;  // elements per block of the device scans
+constexpr int kScanBlock = 1024;    // elements per block of the multi-block scan
+constexpr int kScan1Max = 1 << 16;  // largest scan done by one workgroup
+
+enum Gate { G_ALWAYS = 0, G_FULL = 1, G_MOVERS = 2 };
+
+__device__ __forceinline__ bool gate_open(const int32_t *flags, int gate)
+{
+    if (gate == G_ALWAYS) return true;
+    const bool full = (flags[F_OVERFLOW] | flags[F_FORCE]) != 0;
+    return gate == G_FULL ? full : !full;
+}
 
 __device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
 {
     int64_t r = i % n;
     return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// Exclusive prefix over the lanes of the wave that are set in `mask`.
-__device__ __forceinline__ int lanes_below(uint64_t mask)
-{
-    return __popcll(mask & ((1ull << lane_id()) - 1ull));
 }
 
 template <class V>
@@ -59,20 +63,39 @@ __device__ V block_excl_scan(V v, V *sh, V &total)
 }
 
 // ---------------------------------------------------------------------------
-// device-wide exclusive scan: out[i] = sum_{j<i} in[i], out[n] = total.
-// `gate`, when non-null, must be non-zero for the scan to run.
+// exclusive scans of f(i), i < n: out[i] = sum_{j<i} f(j), out[n] = total
 // ---------------------------------------------------------------------------
-template <class TI, class TO>
-__global__ void __launch_bounds__(256) k_scan_partials(const TI *in, int64_t n, TO *part,
-                                                       const int32_t *gate)
+template <class TO, class F>
+__global__ void __launch_bounds__(1024) k_scan1(F f, int64_t n, TO *out, const int32_t *flags,
+                                                int gate)
 {
-    if (gate && *gate == 0) return;
+    if (!gate_open(flags, gate)) return;
+    __shared__ TO sh[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t i0 = (int64_t)threadIdx.x * per;
+    const int64_t i1 = min(i0 + per, n);
+    TO s = 0;
+    for (int64_t i = i0; i < i1; ++i) s += f(i);
+    TO tot;
+    TO ex = block_excl_scan<TO>(s, sh, tot);
+    for (int64_t i = i0; i < i1; ++i) {
+        out[i] = ex;
+        ex += f(i);
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
+template <class TO, class F>
+__global__ void __launch_bounds__(256) k_scan_partials(F f, int64_t n, TO *part,
+                                                       const int32_t *flags, int gate)
+{
+    if (!gate_open(flags, gate)) return;
     __shared__ TO sh[256];
     int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
     TO s = 0;
     for (int k = 0; k < kScanBlock / 256; ++k) {
         int64_t i = b0 + k * 256 + threadIdx.x;
-        if (i < n) s += (TO)in[i];
+        if (i < n) s += f(i);
     }
     TO tot;
     block_excl_scan<TO>(s, sh, tot);
@@ -80,9 +103,10 @@ __global__ void __launch_bounds__(256) k_scan_partials(const TI *in, int64_t n, 
 }
 
 template <class TO>
-__global__ void __launch_bounds__(256) k_scan_spine(TO *part, int64_t nb, const int32_t *gate)
+__global__ void __launch_bounds__(256) k_scan_spine(TO *part, int64_t nb, const int32_t *flags,
+                                                    int gate)
 {
-    if (gate && *gate == 0) return;
+    if (!gate_open(flags, gate)) return;
     __shared__ TO sh[256];
     TO carry = 0;
     for (int64_t b0 = 0; b0 < nb; b0 += 256) {
@@ -96,20 +120,19 @@ __global__ void __launch_bounds__(256) k_scan_spine(TO *part, int64_t nb, const 
     }
 }
 
-template <class TI, class TO>
-__global__ void __launch_bounds__(256) k_scan_final(const TI *in, int64_t n, const TO *part,
-                                                    TO *out, const int32_t *gate)
+template <class TO, class F>
+__global__ void __launch_bounds__(256) k_scan_final(F f, int64_t n, const TO *part, TO *out,
+                                                    const int32_t *flags, int gate)
 {
-    if (gate && *gate == 0) return;
+    if (!gate_open(flags, gate)) return;
     __shared__ TO sh[256];
     int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
     constexpr int K = kScanBlock / 256;
     TO v[K];
     TO s = 0;
-    // each thread owns K consecutive elements
     for (int k = 0; k < K; ++k) {
         int64_t i = b0 + (int64_t)threadIdx.x * K + k;
-        v[k] = i < n ? (TO)in[i] : TO(0);
+        v[k] = i < n ? f(i) : TO(0);
         s += v[k];
     }
     TO tot;
@@ -122,61 +145,71 @@ __global__ void __launch_bounds__(256) k_scan_final(const TI *in, int64_t n, con
     }
 }
 
-template <class TI, class TO>
-hipError_t scan_excl(const TI *in, TO *out, int64_t n, TO *part, const int32_t *gate,
-                     hipStream_t s)
+template <class TO, class F>
+hipError_t scan(F f, int64_t n, TO *out, TO *part, const int32_t *flags, int gate, hipStream_t s)
 {
+    if (n <= kScan1Max) {
+        hipLaunchKernelGGL((k_scan1<TO, F>), dim3(1), dim3(1024), 0, s, f, n, out, flags, gate);
+        return hipGetLastError();
+    }
     int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-    if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_scan_partials<TI, TO>), dim3(nb), dim3(256), 0, s, in, n, part, gate);
-    hipLaunchKernelGGL((k_scan_spine<TO>), dim3(1), dim3(256), 0, s, part, nb, gate);
-    hipLaunchKernelGGL((k_scan_final<TI, TO>), dim3(nb), dim3(256), 0, s, in, n, part, out,
+    hipLaunchKernelGGL((k_scan_partials<TO, F>), dim3(nb), dim3(256), 0, s, f, n, part, flags,
+                       gate);
+    hipLaunchKernelGGL((k_scan_spine<TO>), dim3(1), dim3(256), 0, s, part, nb, flags, gate);
+    hipLaunchKernelGGL((k_scan_final<TO, F>), dim3(nb), dim3(256), 0, s, f, n, part, out, flags,
                        gate);
     return hipGetLastError();
 }
 
+// arrivals per chunk; also flags a chunk whose new count exceeds its room
+struct ArrivalsCheck {
+    const int32_t *in, *out, *cnt, *room;
+    int32_t *flags;
+    __device__ int32_t operator()(int64_t i) const
+    {
+        const int32_t a = in[i];
+        if ((int64_t)cnt[i] - out[i] + a > room[i]) flags[F_OVERFLOW] = 1;
+        return a;
+    }
+};
+
+// work items per chunk
+struct Segments {
+    const int32_t *cnt;
+    __device__ int32_t operator()(int64_t i) const { return (cnt[i] + kSeg - 1) / kSeg; }
+};
+
+// rooms of a re-binned layout: the spare slots are shared out in proportion
+// to (count + kSlackMin); also records the room
+struct Rooms {
+    const int32_t *new_cnt;
+    int64_t spare, denom;
+    int32_t *nroom;
+    __device__ int64_t operator()(int64_t i) const
+    {
+        const int64_t n = new_cnt[i];
+        const int64_t r = n + (denom > 0 ? spare * (n + kSlackMin) / denom : 0);
+        nroom[i] = (int32_t)r;
+        return r;
+    }
+};
+
 // ---------------------------------------------------------------------------
-// small utilities
+// chunks and re-basing of chunk-local offsets
 // ---------------------------------------------------------------------------
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    int64_t g = (n + 255) / 256;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-template <class A>
-__global__ void k_fill_acc(A *p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = A(0);
-}
-
-// chunk of (chunk coords) and back
 __device__ __forceinline__ int64_t chunk_index(const Params &p, int64_t cx, int64_t cy,
                                                int64_t cz)
 {
     return (cz * p.nc[1] + cy) * p.nc[0] + cx;
 }
 
-// Re-bin of a chunk-local offset that may have left [0, E): returns the
-// chunk shift along the axis and the offset relative to the new chunk.  A
-// rounding that lands exactly on E belongs to the next chunk at offset 0.
+// An offset that left [0, E) moves to the chunk k steps away along the axis
+// and is re-based onto it; a rounding that lands exactly on E belongs to the
+// next chunk at offset 0.  Returns k.
 template <class T>
-__device__ __forceinline__ int rebase(T &xi, int E)
+__device__ __forceinline__ int rebase(T &xi, T fe, T inv_e)
 {
-    const T fe = T(E);
-    T kf = floor(xi / fe);
+    T kf = floor(xi * inv_e);
     int k = (int)kf;
     xi = xi - kf * fe;
     if (xi < T(0)) { xi += fe; --k; }
@@ -187,47 +220,51 @@ __device__ __forceinline__ int rebase(T &xi, int E)
 template <class T>
 __device__ __forceinline__ int64_t chunk_after(const Params &p, int64_t c, T &ox, T &oy, T &oz)
 {
-    int64_t cx = c % p.nc[0];
-    int64_t cy = (c / p.nc[0]) % p.nc[1];
-    int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
-    int kx = rebase(ox, p.E), ky = rebase(oy, p.E), kz = rebase(oz, p.E);
+    const T fe = T(p.E), inv_e = T(1) / T(p.E);  // E is a power of two: exact
+    int kx = rebase(ox, fe, inv_e), ky = rebase(oy, fe, inv_e), kz = rebase(oz, fe, inv_e);
     if ((kx | ky | kz) == 0) return c;
+    const int64_t cx = c % p.nc[0];
+    const int64_t cy = (c / p.nc[0]) % p.nc[1];
+    const int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
     return chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
                        wrapi(cz + kz, p.nc[2]));
 }
 
 // ---------------------------------------------------------------------------
-// work items: one per run of <= kSeg particles of a chunk
+// work items and the per-step reset
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void k_nseg(const View<T> *views, const int32_t *cur, int64_t C, int32_t *nseg)
-{
-    const int32_t *cnt = views[*cur].cnt;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x)
-        nseg[c] = (cnt[c] + kSeg - 1) / kSeg;
-}
-
-__global__ void k_items(const int32_t *nseg_excl, int64_t C, int32_t *items, int32_t *nitems)
+__global__ void k_items(const int32_t *noff, int64_t C, int32_t *items, int32_t *out_cnt,
+                        int32_t *in_cnt, int32_t *new_cnt, int32_t *cursor, int32_t *flags)
 {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
          c += (int64_t)gridDim.x * blockDim.x) {
-        int32_t o = nseg_excl[c], e = nseg_excl[c + 1];
+        const int32_t o = noff[c], e = noff[c + 1];
         for (int32_t s = 0; s < e - o; ++s) {
             items[2 * (int64_t)(o + s)] = (int32_t)c;
             items[2 * (int64_t)(o + s) + 1] = s;
         }
-        if (c == C - 1) *nitems = e;
+        out_cnt[c] = 0;
+        in_cnt[c] = 0;
+        new_cnt[c] = 0;
+        cursor[c] = 0;
+        if (c == C - 1) flags[F_NITEMS] = e;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flags[F_OVERFLOW] = 0;
+        flags[F_FORCE] = 0;
+        flags[F_LASTMOV] = flags[F_NMOV];  // movers of the step just finished
+        flags[F_NMOV] = 0;
     }
 }
+
+__global__ void k_set_flag(int32_t *flags, int which, int32_t v) { flags[which] = v; }
 
 // ---------------------------------------------------------------------------
 // the step kernel
 // ---------------------------------------------------------------------------
 template <class T, class A>
 struct StepArgs {
-    const View<T> *views;
-    const int32_t *cur;
+    View<T> V;
     const int32_t *items;
     const int32_t *nitems;
     const T *u;              // field [3][n2][n1][n0]
@@ -238,9 +275,9 @@ struct StepArgs {
     int32_t *out_cnt;
     int32_t *in_cnt;
     int32_t *hole;
-    int32_t *overflow;
+    int32_t *flags;
     int64_t grid;            // launched workgroups (for the XCD remap)
-    int32_t record;          // write movers (0 only for the tape recompute's dry runs)
+    int32_t deposit;         // 0: move and re-bin only (tape recompute)
     Params p;
     T dt;
     T dt_h[3];               // dt / h per axis
@@ -254,13 +291,38 @@ struct StepArgs {
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t grid)
 {
     const int64_t nx = 8;
-    int64_t per = grid / nx;
-    int64_t rem = grid % nx;
-    int64_t x = bid % nx;
-    int64_t k = bid / nx;
-    // XCD x owns logical items [start_x, start_x + per + (x < rem))
-    int64_t start = x * per + (x < rem ? x : rem);
-    return start + k;
+    const int64_t per = grid / nx, rem = grid % nx;
+    const int64_t x = bid % nx, k = bid / nx;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
+// A mover already written in place (un-rebased offsets, relative to chunk
+// c): records the vacated slot, marks it, and copies the particle, re-based
+// onto its destination chunk, into the mover list at m.
+template <class T, class A>
+__device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, int64_t base,
+                                           int64_t q, int64_t m, int64_t hpos)
+{
+    const View<T> &V = a.V;
+    T x = V.ox[q], y = V.oy[q], z = V.oz[q];
+    const int64_t cn = chunk_after(a.p, c, x, y, z);
+    const int32_t id = V.id[q];
+    V.id[q] = -1 - id;
+    a.hole[base + hpos] = (int32_t)(q - base);
+    if (m < a.mcap) {
+        a.mv.ox[m] = x;
+        a.mv.oy[m] = y;
+        a.mv.oz[m] = z;
+        a.mv.vx[m] = V.vx[q];
+        a.mv.vy[m] = V.vy[q];
+        a.mv.vz[m] = V.vz[q];
+        a.mv.d[m] = V.d[q];
+        a.mv.id[m] = id;
+        a.mv.dest[m] = (int32_t)cn;
+        a.mv.rank[m] = atomicAdd(&a.in_cnt[cn], 1);
+    } else {
+        a.flags[F_OVERFLOW] = 1;
+    }
 }
 
 template <class T, class A, int E, int INTERP>
@@ -271,10 +333,12 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     constexpr int E3 = E * E * E;
     __shared__ T tile[3 * S3];
     __shared__ A acc[3 * E3];
+    __shared__ int32_t mslot[kMoverStage];
+    __shared__ int32_t mcount, mbase_sh, hbase_sh;
 
     const int64_t item = xcd_remap(blockIdx.x, a.grid);
     if (item >= *a.nitems) return;
-    const View<T> V = a.views[*a.cur];
+    const View<T> &V = a.V;
     const int64_t c = a.items[2 * item];
     const int64_t seg = a.items[2 * item + 1];
     const int64_t base = V.base[c];
@@ -288,27 +352,48 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     const int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
     const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
 
+    // first particle of this thread, loaded while the tile is staged
+    int64_t q = s0 + threadIdx.x;
+    bool have = q < s1;
+    T nx = 0, ny = 0, nz = 0, nvx = 0, nvy = 0, nvz = 0, nd = 0;
+    if (have) {
+        nx = V.ox[q]; ny = V.oy[q]; nz = V.oz[q];
+        nvx = V.vx[q]; nvy = V.vy[q]; nvz = V.vz[q];
+        nd = V.d[q];
+    }
+
     // stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped
     for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
-        int comp = t / S3;
-        int r = t - comp * S3;
-        int k = r / (S * S);
-        int j = (r / S) % S;
-        int i = r % S;
-        int64_t gx = wrapi(cx * E - 1 + i, p.n[0]);
-        int64_t gy = wrapi(cy * E - 1 + j, p.n[1]);
-        int64_t gz = wrapi(cz * E - 1 + k, p.n[2]);
+        const int comp = t / S3;
+        const int r = t - comp * S3;
+        const int k = r / (S * S);
+        const int j = (r / S) % S;
+        const int i = r % S;
+        const int64_t gx = wrapi(cx * E - 1 + i, p.n[0]);
+        const int64_t gy = wrapi(cy * E - 1 + j, p.n[1]);
+        const int64_t gz = wrapi(cz * E - 1 + k, p.n[2]);
         tile[t] = a.u[comp * ncell + (gz * p.n[1] + gy) * p.n[0] + gx];
     }
     for (int t = threadIdx.x; t < 3 * E3; t += kBlock) acc[t] = A(0);
+    if (threadIdx.x == 0) mcount = 0;
     __syncthreads();
 
     const T dt = a.dt;
     const A inv_V = (A)p.inv_V;
-    for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock) {
-        T xi[3] = {V.ox[q], V.oy[q], V.oz[q]};
-        T up[3] = {V.vx[q], V.vy[q], V.vz[q]};
-        const T dp = V.d[q];
+    const A dtA = (A)dt;
+    const T fe = T(E), inv_e = T(1) / T(E);
+    while (have) {
+        const T xi[3] = {nx, ny, nz};
+        const T up[3] = {nvx, nvy, nvz};
+        const T dp = nd;
+        const int64_t qc = q;
+        q += kBlock;
+        have = q < s1;
+        if (have) {  // prefetch the next particle of this thread
+            nx = V.ox[q]; ny = V.oy[q]; nz = V.oz[q];
+            nvx = V.vx[q]; nvy = V.vy[q]; nvz = V.vz[q];
+            nd = V.d[q];
+        }
 
         // gather the fluid velocity at the particle
         T uf[3];
@@ -317,8 +402,8 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             T f[3];
             int i0[3];
             for (int ax = 0; ax < 3; ++ax) {
-                T s = xi[ax] - T(0.5);
-                T fl = floor(s);
+                const T s = xi[ax] - T(0.5);
+                const T fl = floor(s);
                 // -1 .. E-1 for offsets in [0, E); clamped so that no state
                 // can index outside the tile
                 i0[ax] = min(max((int)fl, -1), E - 1);
@@ -332,10 +417,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             const T w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
             for (int comp = 0; comp < 3; ++comp) {
                 const T *tc = tile + comp * S3 + t0;
-                T r00 = wx0 * tc[0] + wx1 * tc[1];
-                T r10 = wx0 * tc[S] + wx1 * tc[S + 1];
-                T r01 = wx0 * tc[S * S] + wx1 * tc[S * S + 1];
-                T r11 = wx0 * tc[S * S + S] + wx1 * tc[S * S + S + 1];
+                const T r00 = wx0 * tc[0] + wx1 * tc[1];
+                const T r10 = wx0 * tc[S] + wx1 * tc[S + 1];
+                const T r01 = wx0 * tc[S * S] + wx1 * tc[S * S + 1];
+                const T r11 = wx0 * tc[S * S + S] + wx1 * tc[S * S + S + 1];
                 uf[comp] = w00 * r00 + w10 * r10 + w01 * r01 + w11 * r11;
             }
         } else {
@@ -357,75 +442,68 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
         }
 
         // drag impulse J = m (u_p' - u_p - g dt) = m dt (u_f - u_p - g dt) / (tau + dt),
-        // evaluated in the accumulator precision from the stored inputs
-        const A dA = (A)dp;
-        const A mass = (A)p.mass_coef * dA * dA * dA;
-        const A tauA = (A)p.tau_coef * dA * dA;
-        const A dtA = (A)dt;
-        const A coef = -mass * dtA / (tauA + dtA) * inv_V;   // -(m dt / (tau+dt)) / V
-        const int cell = (cl[2] * E + cl[1]) * E + cl[0];
-        for (int ax = 0; ax < 3; ++ax) {
-            A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
-            atomicAdd(&acc[ax * E3 + cell], coef * slip);
+        // in the accumulator precision from the stored inputs; the fluid
+        // receives -J / V in the start-of-step cell
+        if (a.deposit) {
+            const A dA = (A)dp;
+            const A mass = (A)p.mass_coef * dA * dA * dA;
+            const A tauA = (A)p.tau_coef * dA * dA;
+            const A coef = -mass * dtA / (tauA + dtA) * inv_V;
+            const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+            for (int ax = 0; ax < 3; ++ax) {
+                const A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
+                atomicAdd(&acc[ax * E3 + cell], coef * slip);
+            }
         }
 
-        // relocate
+        // relocate: stayers keep re-based offsets; movers keep un-rebased
+        // ones (relative to this chunk) until they are emitted
         T xr[3] = {xn[0], xn[1], xn[2]};
-        const int64_t cn = chunk_after(p, c, xr[0], xr[1], xr[2]);
-        const bool mover = cn != c;
-        V.vx[q] = upn[0];
-        V.vy[q] = upn[1];
-        V.vz[q] = upn[2];
-        // stayers keep their re-based offsets; movers keep the un-rebased
-        // ones (relative to this chunk) so that a full re-bin can re-key them
-        V.ox[q] = mover ? xn[0] : xr[0];
-        V.oy[q] = mover ? xn[1] : xr[1];
-        V.oz[q] = mover ? xn[2] : xr[2];
-
-        const uint64_t mask = __ballot(mover);
-        if (mask) {
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            const int nw = __popcll(mask);
-            const int below = lanes_below(mask);
-            int32_t mbase = 0, hbase = 0;
-            if (lane_id() == leader) {
-                mbase = atomicAdd(a.nmov, nw);
-                hbase = atomicAdd(&a.out_cnt[c], nw);
-            }
-            mbase = __shfl(mbase, leader);
-            hbase = __shfl(hbase, leader);
-            if (mover) {
-                const int32_t id = V.id[q];
-                V.id[q] = -1 - id;
-                a.hole[base + hbase + below] = (int32_t)(q - base);
-                const int64_t m = (int64_t)mbase + below;
-                if (a.record && m < a.mcap) {
-                    a.mv.ox[m] = xr[0];
-                    a.mv.oy[m] = xr[1];
-                    a.mv.oz[m] = xr[2];
-                    a.mv.vx[m] = upn[0];
-                    a.mv.vy[m] = upn[1];
-                    a.mv.vz[m] = upn[2];
-                    a.mv.d[m] = dp;
-                    a.mv.id[m] = id;
-                    a.mv.dest[m] = (int32_t)cn;
-                    a.mv.rank[m] = atomicAdd(&a.in_cnt[cn], 1);
-                } else {
-                    *a.overflow = 1;
-                }
+        const int kx = rebase(xr[0], fe, inv_e);
+        const int ky = rebase(xr[1], fe, inv_e);
+        const int kz = rebase(xr[2], fe, inv_e);
+        const bool mover = (kx | ky | kz) != 0;
+        V.ox[qc] = mover ? xn[0] : xr[0];
+        V.oy[qc] = mover ? xn[1] : xr[1];
+        V.oz[qc] = mover ? xn[2] : xr[2];
+        V.vx[qc] = upn[0];
+        V.vy[qc] = upn[1];
+        V.vz[qc] = upn[2];
+        if (mover) {
+            const int k = atomicAdd(&mcount, 1);
+            if (k < kMoverStage) {
+                mslot[k] = (int32_t)(qc - base);
+            } else {  // more movers than the LDS stage holds: emit directly
+                const int64_t m = atomicAdd(a.nmov, 1);
+                const int64_t h = atomicAdd(&a.out_cnt[c], 1);
+                emit_mover(a, c, base, qc, m, h);
             }
         }
     }
     __syncthreads();
 
     // flush the chunk's accumulated source
-    A *dst = a.src + c * (3 * E3);
-    for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
-        A v = acc[t];
-        if (v != A(0)) {
-            if (multi) atomicAdd(dst + t, v);
-            else dst[t] += v;
+    if (a.deposit) {
+        A *dst = a.src + c * (3 * E3);
+        for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
+            const A v = acc[t];
+            if (v != A(0)) {
+                if (multi) atomicAdd(dst + t, v);
+                else dst[t] += v;
+            }
         }
+    }
+
+    // emit the staged movers with one reservation per workgroup
+    const int nm = min(mcount, kMoverStage);
+    if (nm > 0) {
+        if (threadIdx.x == 0) {
+            mbase_sh = atomicAdd(a.nmov, nm);
+            hbase_sh = atomicAdd(&a.out_cnt[c], nm);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < nm; j += kBlock)
+            emit_mover(a, c, base, base + mslot[j], (int64_t)mbase_sh + j, (int64_t)hbase_sh + j);
     }
 }
 
@@ -433,26 +511,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
 // mover-only re-bin
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void k_check(const View<T> *views, const int32_t *cur, int64_t C,
-                        const int32_t *out_cnt, const int32_t *in_cnt, const int32_t *nmov,
-                        int64_t mcap, int32_t *flags)
-{
-    const View<T> V = views[*cur];
-    int bad = 0;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int64_t nc = (int64_t)V.cnt[c] - out_cnt[c] + in_cnt[c];
-        if (nc > V.room[c]) bad = 1;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && *nmov > mcap) bad = 1;
-    if (bad) flags[F_OVERFLOW] = 1;
-}
-
-template <class T>
 __global__ void k_inbox(const Movers<T> mv, const int32_t *nmov, int64_t mcap,
                         const int32_t *in_off, int32_t *inbox, const int32_t *flags)
 {
-    if (flags[F_OVERFLOW] | flags[F_FORCE]) return;
+    if (!gate_open(flags, G_MOVERS)) return;
     const int64_t n = min((int64_t)*nmov, mcap);
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
          m += (int64_t)gridDim.x * blockDim.x)
@@ -487,15 +549,13 @@ __device__ __forceinline__ void place_mover(const View<T> &V, int64_t dst, const
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_fill(const View<T> *views, const int32_t *cur, int64_t C,
-                                              const int32_t *out_cnt, const int32_t *in_cnt,
-                                              const int32_t *in_off, const int32_t *inbox,
-                                              const Movers<T> mv, int32_t *hole,
-                                              const int32_t *flags)
+__global__ void __launch_bounds__(256) k_fill(View<T> V, int64_t C, const int32_t *out_cnt,
+                                              const int32_t *in_cnt, const int32_t *in_off,
+                                              const int32_t *inbox, const Movers<T> mv,
+                                              int32_t *hole, const int32_t *flags)
 {
-    if (flags[F_OVERFLOW] | flags[F_FORCE]) return;
+    if (!gate_open(flags, G_MOVERS)) return;
     __shared__ int32_t sh[256];
-    const View<T> V = views[*cur];
     for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
         const int32_t out = out_cnt[c], in = in_cnt[c];
         if (out == 0 && in == 0) continue;
@@ -508,18 +568,18 @@ __global__ void __launch_bounds__(256) k_fill(const View<T> *views, const int32_
             // every vacated slot lies below the new count: arrivals fill
             // them first, then extend the chunk
             for (int32_t r = threadIdx.x; r < in; r += blockDim.x) {
-                int64_t dst = base + (r < out ? H[r] : cnt + (r - out));
+                const int64_t dst = base + (r < out ? H[r] : cnt + (r - out));
                 place_mover(V, dst, mv, box[r]);
             }
         } else {
-            // keep the vacated slots below the new count (in place)
+            // keep the vacated slots below the new count (compacted in place)
             int32_t k = 0;
             for (int32_t j0 = 0; j0 < out; j0 += blockDim.x) {
-                int32_t j = j0 + threadIdx.x;
-                int32_t h = j < out ? H[j] : 0;
-                int32_t keep = (j < out && h < ncnt) ? 1 : 0;
+                const int32_t j = j0 + threadIdx.x;
+                const int32_t h = j < out ? H[j] : 0;
+                const int32_t keep = (j < out && h < ncnt) ? 1 : 0;
                 int32_t tot;
-                int32_t ex = block_excl_scan<int32_t>(keep, sh, tot);
+                const int32_t ex = block_excl_scan<int32_t>(keep, sh, tot);
                 if (keep) H[k + ex] = h;
                 k += tot;
                 __syncthreads();
@@ -531,11 +591,11 @@ __global__ void __launch_bounds__(256) k_fill(const View<T> *views, const int32_
             int32_t placed = 0;
             const int32_t tail = cnt - ncnt;
             for (int32_t t0 = 0; t0 < tail; t0 += blockDim.x) {
-                int32_t t = t0 + threadIdx.x;
-                int64_t slot = base + ncnt + t;
-                int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
+                const int32_t t = t0 + threadIdx.x;
+                const int64_t slot = base + ncnt + t;
+                const int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
                 int32_t tot;
-                int32_t ex = block_excl_scan<int32_t>(live, sh, tot);
+                const int32_t ex = block_excl_scan<int32_t>(live, sh, tot);
                 if (live) copy_slot(V, base + H[in + placed + ex], slot);
                 placed += tot;
                 __syncthreads();
@@ -547,16 +607,15 @@ __global__ void __launch_bounds__(256) k_fill(const View<T> *views, const int32_
 }
 
 // ---------------------------------------------------------------------------
-// full re-bin (counting sort into the other store)
+// full re-bin: counting sort into the second store, then copied back
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_rekey_count(const View<T> *views, const int32_t *cur,
-                                                     const int32_t *items, const int32_t *nitems,
-                                                     Params p, const Movers<T> mv, int64_t npend,
+__global__ void __launch_bounds__(256) k_rekey_count(View<T> V, const int32_t *items,
+                                                     const int32_t *nitems, Params p,
+                                                     const Movers<T> mv, int64_t npend,
                                                      int32_t *new_cnt, const int32_t *flags)
 {
-    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
-    const View<T> V = views[*cur];
+    if (!gate_open(flags, G_FULL)) return;
     const int64_t ni = *nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
         const int64_t c = items[2 * it], seg = items[2 * it + 1];
@@ -564,8 +623,15 @@ __global__ void __launch_bounds__(256) k_rekey_count(const View<T> *views, const
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            int64_t cn = chunk_after(p, c, x, y, z);
-            atomicAdd(&new_cnt[cn], 1);
+            const int64_t cn = chunk_after(p, c, x, y, z);
+            // one atomic per wave for the lanes that stay in chunk c
+            const uint64_t stay = __ballot(cn == c);
+            if (cn == c) {
+                if (__lane_id() == __ffsll((unsigned long long)stay) - 1)
+                    atomicAdd(&new_cnt[c], __popcll(stay));
+            } else {
+                atomicAdd(&new_cnt[cn], 1);
+            }
         }
     }
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
@@ -573,31 +639,14 @@ __global__ void __launch_bounds__(256) k_rekey_count(const View<T> *views, const
         atomicAdd(&new_cnt[mv.dest[m]], 1);
 }
 
-__global__ void k_rooms(const int32_t *new_cnt, int64_t C, int64_t slots, int64_t total,
-                        int32_t *room_out, const int32_t *flags)
-{
-    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
-    // spare slots shared out in proportion to (count + kSlackMin)
-    const int64_t spare = slots - total;
-    const int64_t denom = total + (int64_t)kSlackMin * C;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int64_t n = new_cnt[c];
-        int64_t extra = denom > 0 ? (spare * (n + kSlackMin)) / denom : 0;
-        room_out[c] = (int32_t)(n + extra);
-    }
-}
-
 template <class T>
-__global__ void __launch_bounds__(256) k_rekey_scatter(const View<T> *views, const int32_t *cur,
-                                                       const int32_t *items, const int32_t *nitems,
-                                                       Params p, const Movers<T> mv, int64_t npend,
+__global__ void __launch_bounds__(256) k_rekey_scatter(View<T> V, View<T> W, const int32_t *items,
+                                                       const int32_t *nitems, Params p,
+                                                       const Movers<T> mv, int64_t npend,
                                                        const int64_t *nbase, int32_t *cursor,
                                                        const int32_t *flags)
 {
-    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
-    const View<T> V = views[*cur];
-    const View<T> W = views[1 - *cur];
+    if (!gate_open(flags, G_FULL)) return;
     const int64_t ni = *nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
         const int64_t c = items[2 * it], seg = items[2 * it + 1];
@@ -605,8 +654,18 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(const View<T> *views, con
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            int64_t cn = chunk_after(p, c, x, y, z);
-            int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+            const int64_t cn = chunk_after(p, c, x, y, z);
+            int64_t dst;
+            const uint64_t stay = __ballot(cn == c);
+            if (cn == c) {
+                const int leader = __ffsll((unsigned long long)stay) - 1;
+                int32_t b = 0;
+                if (__lane_id() == leader) b = atomicAdd(&cursor[c], __popcll(stay));
+                b = __shfl(b, leader);
+                dst = nbase[c] + b + __popcll(stay & ((1ull << __lane_id()) - 1ull));
+            } else {
+                dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+            }
             W.ox[dst] = x;
             W.oy[dst] = y;
             W.oz[dst] = z;
@@ -614,14 +673,14 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(const View<T> *views, con
             W.vy[dst] = V.vy[q];
             W.vz[dst] = V.vz[q];
             W.d[dst] = V.d[q];
-            int32_t id = V.id[q];
+            const int32_t id = V.id[q];
             W.id[dst] = id < 0 ? -1 - id : id;
         }
     }
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
          m += (int64_t)gridDim.x * blockDim.x) {
-        int64_t cn = mv.dest[m];
-        int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+        const int64_t cn = mv.dest[m];
+        const int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
         W.ox[dst] = mv.ox[m];
         W.oy[dst] = mv.oy[m];
         W.oz[dst] = mv.oz[m];
@@ -634,43 +693,29 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(const View<T> *views, con
 }
 
 template <class T>
-__global__ void k_rekey_finish(const View<T> *views, const int32_t *cur, int64_t C,
+__global__ void k_rekey_commit(View<T> V, View<T> W, int64_t slots, int64_t C,
                                const int32_t *new_cnt, const int64_t *nbase,
-                               const int32_t *nroom, const int32_t *flags)
+                               const int32_t *nroom, int32_t *flags)
 {
-    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
-    const View<T> W = views[1 - *cur];
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        W.cnt[c] = new_cnt[c];
-        W.base[c] = nbase[c];
-        W.room[c] = nroom[c];
+    if (!gate_open(flags, G_FULL)) return;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = g0; q < slots; q += gs) {
+        V.ox[q] = W.ox[q];
+        V.oy[q] = W.oy[q];
+        V.oz[q] = W.oz[q];
+        V.vx[q] = W.vx[q];
+        V.vy[q] = W.vy[q];
+        V.vz[q] = W.vz[q];
+        V.d[q] = W.d[q];
+        V.id[q] = W.id[q];
     }
-}
-
-__global__ void k_flip(int32_t *cur, int32_t *flags)
-{
-    if (!(flags[F_OVERFLOW] | flags[F_FORCE])) return;
-    *cur = 1 - *cur;
-    flags[F_REPACKS] += 1;
-}
-
-// per-step reset of counters
-__global__ void k_reset(int64_t C, int32_t *out_cnt, int32_t *in_cnt, int32_t *new_cnt,
-                        int32_t *cursor, int32_t *flags, int32_t force)
-{
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        out_cnt[c] = 0;
-        in_cnt[c] = 0;
-        new_cnt[c] = 0;
-        cursor[c] = 0;
+    for (int64_t c = g0; c < C; c += gs) {
+        V.cnt[c] = new_cnt[c];
+        V.base[c] = nbase[c];
+        V.room[c] = nroom[c];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        flags[F_OVERFLOW] = 0;
-        flags[F_NMOV] = 0;
-        flags[F_FORCE] = force;
-    }
+    if (g0 == 0) flags[F_REPACKS] += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -697,12 +742,12 @@ __global__ void k_stage(int64_t n, const double *x, const double *up, const doub
             if (ci < 0) { g += p.n[a]; ci += p.n[a]; }
             ch[a] = ci / p.E;
             T o = (T)(g - (double)(ch[a] * p.E));   // exact before the rounding to T
-            int k = rebase(o, p.E);
+            const int k = rebase(o, T(p.E), T(1) / T(p.E));
             ch[a] = wrapi(ch[a] + k, p.nc[a]);
             loc[a] = o;
         }
-        double v[3] = {up[3 * i], up[3 * i + 1], up[3 * i + 2]};
-        double dd = d[i];
+        const double v[3] = {up[3 * i], up[3 * i + 1], up[3 * i + 2]};
+        const double dd = d[i];
         for (int a = 0; a < 3; ++a)
             if (!isfinite(v[a])) ok = false;
         if (!isfinite(dd) || !(dd > 0.0)) ok = false;
@@ -725,13 +770,11 @@ __global__ void k_stage(int64_t n, const double *x, const double *up, const doub
 // outputs
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void __launch_bounds__(256) k_get_particles(const View<T> *views, const int32_t *cur,
-                                                       const int32_t *items, const int32_t *nitems,
-                                                       Params p, int64_t count, double *x,
-                                                       double *up, double *d, int64_t *id,
-                                                       int32_t *cell)
+__global__ void __launch_bounds__(256) k_get_particles(View<T> V, const int32_t *items,
+                                                       const int32_t *nitems, Params p,
+                                                       int64_t count, double *x, double *up,
+                                                       double *d, int64_t *id, int32_t *cell)
 {
-    const View<T> V = views[*cur];
     const int64_t ni = *nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
         const int64_t c = items[2 * it], seg = items[2 * it + 1];
@@ -776,25 +819,45 @@ __global__ void k_get_sources(A *src, Params p, double *out, int reset)
     }
 }
 
+template <class A>
+__global__ void k_fill_acc(A *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = A(0);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 // synthetic fluid update: U^k = R_z(theta_k) U^0, rounded once to T
 template <class T>
 __global__ void k_rotate(const T *u0, T *u, int64_t ncell, double cs, double sn)
 {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < ncell;
          q += (int64_t)gridDim.x * blockDim.x) {
-        double ux = (double)u0[q], uy = (double)u0[ncell + q];
+        const double ux = (double)u0[q], uy = (double)u0[ncell + q];
         u[q] = (T)(cs * ux - sn * uy);
         u[ncell + q] = (T)(sn * ux + cs * uy);
         u[2 * ncell + q] = u0[2 * ncell + q];
     }
 }
 
-// checkpoint copy of the current store (all slots) and its layout
+// checkpoint copy of the store (all slots) and its layout
 template <class T>
-__global__ void k_snapshot(const View<T> *views, const int32_t *cur, int64_t slots, int64_t C,
-                           char *buf, int restore)
+__global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, int restore)
 {
-    const View<T> V = views[*cur];
     T *arr[7] = {V.ox, V.oy, V.oz, V.vx, V.vy, V.vz, V.d};
     T *sT = reinterpret_cast<T *>(buf);
     int32_t *sid = reinterpret_cast<int32_t *>(sT + 7 * slots);
@@ -834,6 +897,24 @@ inline int64_t grid_for(int64_t n, int64_t cap = 8192)
     int64_t g = (n + 255) / 256;
     if (g < 1) g = 1;
     return g > cap ? cap : g;
+}
+
+template <class T>
+View<T> view_of(st_ctx *c, int b)
+{
+    View<T> v;
+    v.ox = (T *)c->store[b][0];
+    v.oy = (T *)c->store[b][1];
+    v.oz = (T *)c->store[b][2];
+    v.vx = (T *)c->store[b][3];
+    v.vy = (T *)c->store[b][4];
+    v.vz = (T *)c->store[b][5];
+    v.d = (T *)c->store[b][6];
+    v.id = (int32_t *)c->store[b][7];
+    v.base = c->base;
+    v.room = c->room;
+    v.cnt = c->cnt;
+    return v;
 }
 
 template <class T>
@@ -877,109 +958,61 @@ hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
                               : launch_step_t<T, A, E, 0>(c, a, s);
 }
 
+// the full re-bin, gated on the device (overflow or force flag)
+template <class T>
+hipError_t launch_rekey(st_ctx *c, int64_t npend, hipStream_t s)
+{
+    const View<T> V = view_of<T>(c, 0), W = view_of<T>(c, 1);
+    const Movers<T> mv = movers_of<T>(c);
+    const int64_t C = c->C;
+    const int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
+    const int64_t total = c->count + npend;
+    hipLaunchKernelGGL((k_rekey_count<T>), dim3(gi), dim3(256), 0, s, V, c->items,
+                       c->flags + F_NITEMS, c->prm, mv, npend, c->new_cnt, c->flags);
+    Rooms rooms{c->new_cnt, c->slots - total, total + (int64_t)kSlackMin * C, c->nroom};
+    hipError_t e = scan<int64_t>(rooms, C, c->nbase, c->scan_tmp, c->flags, G_FULL, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gi), dim3(256), 0, s, V, W, c->items,
+                       c->flags + F_NITEMS, c->prm, mv, npend, c->nbase, c->cursor, c->flags);
+    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, V,
+                       W, c->slots, C, c->new_cnt, c->nbase, c->nroom, c->flags);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_init_views(st_ctx *c, hipStream_t s)
-{
-    return dispatch(c, [&](auto t, auto) -> hipError_t {
-        using T = decltype(t);
-        View<T> v[2];
-        for (int b = 0; b < 2; ++b) {
-            v[b].ox = (T *)c->store[b][0];
-            v[b].oy = (T *)c->store[b][1];
-            v[b].oz = (T *)c->store[b][2];
-            v[b].vx = (T *)c->store[b][3];
-            v[b].vy = (T *)c->store[b][4];
-            v[b].vz = (T *)c->store[b][5];
-            v[b].d = (T *)c->store[b][6];
-            v[b].id = (int32_t *)c->store[b][7];
-            v[b].base = c->base[b];
-            v[b].room = c->room[b];
-            v[b].cnt = c->cnt[b];
-        }
-        hipError_t e = hipMemcpyAsync(c->views, v, sizeof v, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return e;
-        return hipStreamSynchronize(s);
-    });
-}
-
 hipError_t launch_items(st_ctx *c, hipStream_t s)
 {
-    return dispatch(c, [&](auto t, auto) -> hipError_t {
-        using T = decltype(t);
-        const View<T> *views = (const View<T> *)c->views;
-        int32_t *nseg = c->nseg;
-        int32_t *noff = c->nseg + c->C + 1;
-        hipLaunchKernelGGL((k_nseg<T>), dim3(grid_for(c->C)), dim3(256), 0, s, views, c->cur,
-                           c->C, nseg);
-        hipError_t e = scan_excl<int32_t, int32_t>(nseg, noff, c->C, (int32_t *)c->scan_tmp,
-                                                   nullptr, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_items, dim3(grid_for(c->C)), dim3(256), 0, s, noff, c->C, c->items,
-                           c->flags + F_NITEMS);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_rebin(st_ctx *c, int force_full, hipStream_t s)
-{
-    (void)force_full;  // the force flag was set on the device by the reset
-    return dispatch(c, [&](auto t, auto) -> hipError_t {
-        using T = decltype(t);
-        const View<T> *views = (const View<T> *)c->views;
-        const Movers<T> mv = movers_of<T>(c);
-        const int64_t C = c->C;
-        hipLaunchKernelGGL((k_check<T>), dim3(grid_for(C)), dim3(256), 0, s, views, c->cur, C,
-                           c->out_cnt, c->in_cnt, c->flags + F_NMOV, c->mcap, c->flags);
-        hipError_t e = scan_excl<int32_t, int32_t>(c->in_cnt, c->in_off, C,
-                                                   (int32_t *)c->scan_tmp, nullptr, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_inbox<T>), dim3(grid_for(c->mcap)), dim3(256), 0, s, mv,
-                           c->flags + F_NMOV, c->mcap, c->in_off, c->inbox, c->flags);
-        int64_t gf = C < 65536 ? C : 65536;
-        hipLaunchKernelGGL((k_fill<T>), dim3(gf), dim3(256), 0, s, views, c->cur, C, c->out_cnt,
-                           c->in_cnt, c->in_off, c->inbox, mv, c->hole, c->flags);
-        // full re-bin, gated on the device by the overflow / force flags
-        const int64_t total = c->count + c->pending;
-        int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
-        hipLaunchKernelGGL((k_rekey_count<T>), dim3(gi), dim3(256), 0, s, views, c->cur, c->items,
-                           c->flags + F_NITEMS, c->prm, mv, c->pending, c->new_cnt, c->flags);
-        hipLaunchKernelGGL(k_rooms, dim3(grid_for(C)), dim3(256), 0, s, c->new_cnt, C, c->slots,
-                           total, c->nroom, c->flags);
-        e = scan_excl<int32_t, int64_t>(c->nroom, c->nbase, C, c->scan_tmp, nullptr, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gi), dim3(256), 0, s, views, c->cur,
-                           c->items, c->flags + F_NITEMS, c->prm, mv, c->pending, c->nbase,
-                           c->cursor, c->flags);
-        hipLaunchKernelGGL((k_rekey_finish<T>), dim3(grid_for(C)), dim3(256), 0, s, views, c->cur,
-                           C, c->new_cnt, c->nbase, c->nroom, c->flags);
-        hipLaunchKernelGGL(k_flip, dim3(1), dim3(1), 0, s, c->cur, c->flags);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return launch_items(c, s);
-    });
-}
-
-hipError_t launch_reset(st_ctx *c, int force, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_reset, dim3(grid_for(c->C)), dim3(256), 0, s, c->C, c->out_cnt,
-                       c->in_cnt, c->new_cnt, c->cursor, c->flags, force);
+    hipError_t e = scan<int32_t>(Segments{c->cnt}, c->C, c->nseg, (int32_t *)c->scan_tmp,
+                                 c->flags, G_ALWAYS, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_items, dim3(grid_for(c->C)), dim3(256), 0, s, c->nseg, c->C, c->items,
+                       c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags);
     return hipGetLastError();
 }
 
-hipError_t launch_step(st_ctx *c, const void *u, double dt, int record, hipStream_t s)
+hipError_t launch_init(st_ctx *c, hipStream_t s)
 {
-    hipError_t e = launch_reset(c, 0, s);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->cnt, c->C, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->room, c->C, 0);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(c->C + 1)), dim3(256), 0, s, c->base, c->C + 1,
+                       (int64_t)0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, c->flags, (int64_t)F_COUNT, 0);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = dispatch(c, [&](auto t, auto acc) -> hipError_t {
+    return launch_items(c, s);
+}
+
+hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStream_t s)
+{
+    return dispatch(c, [&](auto t, auto acc) -> hipError_t {
         using T = decltype(t);
         using A = decltype(acc);
         StepArgs<T, A> a;
-        a.views = (const View<T> *)c->views;
-        a.cur = c->cur;
+        a.V = view_of<T>(c, 0);
         a.items = c->items;
         a.nitems = c->flags + F_NITEMS;
         a.u = (const T *)u;
@@ -990,9 +1023,9 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int record, hipStrea
         a.out_cnt = c->out_cnt;
         a.in_cnt = c->in_cnt;
         a.hole = c->hole;
-        a.overflow = c->flags + F_OVERFLOW;
+        a.flags = c->flags;
         a.grid = c->max_items;
-        a.record = record;
+        a.deposit = deposit;
         a.p = c->prm;
         a.dt = (T)dt;
         for (int ax = 0; ax < 3; ++ax) {
@@ -1000,21 +1033,54 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int record, hipStrea
             a.g[ax] = (T)c->prm.g[ax];
         }
         a.tau_coef = (T)c->prm.tau_coef;
-        switch (c->prm.E) {
-        case 2: return launch_step_e<T, A, 2>(c, a, s);
-        case 4: return launch_step_e<T, A, 4>(c, a, s);
-        default: return launch_step_e<T, A, 8>(c, a, s);
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        if (c->timing) {
+            for (int k = 0; k < 2; ++k) {
+                hipError_t ee = hipEventCreate(&ev[k]);
+                if (ee != hipSuccess) return ee;
+                c->tev.push_back(ev[k]);
+            }
+            hipError_t ee = hipEventRecord(ev[0], s);
+            if (ee != hipSuccess) return ee;
         }
+        hipError_t r;
+        switch (c->prm.E) {
+        case 2: r = launch_step_e<T, A, 2>(c, a, s); break;
+        case 4: r = launch_step_e<T, A, 4>(c, a, s); break;
+        default: r = launch_step_e<T, A, 8>(c, a, s); break;
+        }
+        if (r == hipSuccess && c->timing) r = hipEventRecord(ev[1], s);
+        if (r != hipSuccess) return r;
+
+        // mover-only re-bin (gated off on the device when a full re-bin is due)
+        const View<T> V = a.V;
+        const Movers<T> mv = a.mv;
+        const int64_t C = c->C;
+        ArrivalsCheck chk{c->in_cnt, c->out_cnt, c->cnt, c->room, c->flags};
+        r = scan<int32_t>(chk, C, c->in_off, (int32_t *)c->scan_tmp, c->flags, G_ALWAYS, s);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL((k_inbox<T>), dim3(grid_for(c->mcap, 2048)), dim3(256), 0, s, mv,
+                           c->flags + F_NMOV, c->mcap, c->in_off, c->inbox, c->flags);
+        const int64_t gf = C < 65536 ? C : 65536;
+        hipLaunchKernelGGL((k_fill<T>), dim3(gf), dim3(256), 0, s, V, C, c->out_cnt, c->in_cnt,
+                           c->in_off, c->inbox, mv, c->hole, c->flags);
+        r = hipGetLastError();
+        if (r != hipSuccess) return r;
+        r = launch_rekey<T>(c, 0, s);
+        if (r != hipSuccess) return r;
+        return launch_items(c, s);
     });
-    if (e != hipSuccess) return e;
-    return launch_rebin(c, 0, s);
 }
 
 hipError_t launch_flush_pending(st_ctx *c, hipStream_t s)
 {
-    hipError_t e = launch_reset(c, 1, s);
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->flags, (int)F_FORCE, 1);
+    hipError_t e = dispatch(c, [&](auto t, auto) -> hipError_t {
+        using T = decltype(t);
+        return launch_rekey<T>(c, c->pending, s);
+    });
     if (e != hipSuccess) return e;
-    return launch_rebin(c, 1, s);
+    return launch_items(c, s);
 }
 
 hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,
@@ -1023,8 +1089,7 @@ hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const doub
     return dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
         hipLaunchKernelGGL((k_stage<T>), dim3(grid_for(n)), dim3(256), 0, s, n, x, up, d, at,
-                           c->next_id, c->prm, movers_of<T>(c),
-                           c->flags);
+                           c->next_id, c->prm, movers_of<T>(c), c->flags);
         return hipGetLastError();
     });
 }
@@ -1034,10 +1099,9 @@ hipError_t launch_get_particles(st_ctx *c, double *x, double *up, double *d, int
 {
     return dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
-        int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
-        hipLaunchKernelGGL((k_get_particles<T>), dim3(gi), dim3(256), 0, s,
-                           (const View<T> *)c->views, c->cur, c->items, c->flags + F_NITEMS,
-                           c->prm, c->count, x, up, d, id, cell);
+        const int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
+        hipLaunchKernelGGL((k_get_particles<T>), dim3(gi), dim3(256), 0, s, view_of<T>(c, 0),
+                           c->items, c->flags + F_NITEMS, c->prm, c->count, x, up, d, id, cell);
         return hipGetLastError();
     });
 }
@@ -1046,9 +1110,9 @@ hipError_t launch_get_sources(st_ctx *c, double *out, int reset, hipStream_t s)
 {
     return dispatch(c, [&](auto, auto acc) -> hipError_t {
         using A = decltype(acc);
-        int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
-        hipLaunchKernelGGL((k_get_sources<A>), dim3(grid_for(n)), dim3(256), 0, s, (A *)c->src,
-                           c->prm, out, reset);
+        const int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        hipLaunchKernelGGL((k_get_sources<A>), dim3(grid_for(n, 16384)), dim3(256), 0, s,
+                           (A *)c->src, c->prm, out, reset);
         return hipGetLastError();
     });
 }
@@ -1057,20 +1121,26 @@ hipError_t launch_zero_sources(st_ctx *c, hipStream_t s)
 {
     return dispatch(c, [&](auto, auto acc) -> hipError_t {
         using A = decltype(acc);
-        int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
-        hipLaunchKernelGGL((k_fill_acc<A>), dim3(grid_for(n)), dim3(256), 0, s, (A *)c->src, n);
+        const int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        hipLaunchKernelGGL((k_fill_acc<A>), dim3(grid_for(n, 16384)), dim3(256), 0, s,
+                           (A *)c->src, n);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) { return fill_i32(p, n, 0, s); }
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, n, 0);
+    return hipGetLastError();
+}
 
 hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, double sn,
                                hipStream_t s)
 {
     return dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
-        int64_t ncell = (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+        const int64_t ncell = (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
         hipLaunchKernelGGL((k_rotate<T>), dim3(grid_for(ncell, 16384)), dim3(256), 0, s,
                            (const T *)u0, (T *)out, ncell, cs, sn);
         return hipGetLastError();
@@ -1079,7 +1149,7 @@ hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, 
 
 size_t snapshot_bytes(const st_ctx *c)
 {
-    size_t head = (7 * (size_t)c->slots * c->tsize + (size_t)c->slots * 4 + 7) & ~(size_t)7;
+    const size_t head = (7 * (size_t)c->slots * c->tsize + (size_t)c->slots * 4 + 7) & ~(size_t)7;
     return head + (size_t)c->C * 16;
 }
 
@@ -1087,12 +1157,10 @@ hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s)
 {
     return dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
-        hipLaunchKernelGGL((k_snapshot<T>), dim3(grid_for(c->slots)), dim3(256), 0, s,
-                           (const View<T> *)c->views, c->cur, c->slots, c->C, (char *)dst,
-                           restore);
+        hipLaunchKernelGGL((k_snapshot<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s,
+                           view_of<T>(c, 0), c->slots, c->C, (char *)dst, restore);
         return hipGetLastError();
     });
 }
 
 }  // namespace st
-

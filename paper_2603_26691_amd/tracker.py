@@ -160,7 +160,16 @@ class Tracker:
         return (f.value, s.value, t.value) if timed else None
 
     def stats(self):
-        m, r, p, s = (ctypes.c_int64() for _ in range(4))
+        m, r, p, s, i = (ctypes.c_int64() for _ in range(5))
         N.check(N.lib().st_stats(self.ctx, ctypes.byref(m), ctypes.byref(r), ctypes.byref(p),
-                                 ctypes.byref(s), _stream()), self.ctx)
-        return {"movers": m.value, "repacks": r.value, "particles": p.value, "slots": s.value}
+                                 ctypes.byref(s), ctypes.byref(i), _stream()), self.ctx)
+        return {"movers": m.value, "repacks": r.value, "particles": p.value, "slots": s.value,
+                "items": i.value}
+
+    def timing(self, enable):
+        """Starts (True) or stops (False) timing the step kernel; returns
+        (summed ms, launches) measured so far."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        N.check(N.lib().st_timing(self.ctx, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n)),
+                self.ctx)
+        return ms.value, n.value
