@@ -49,7 +49,7 @@ void free_all(st_ctx *c)
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 8; ++k) (void)hipFree(c->store[b][k]);
     for (int k = 0; k < 10; ++k) (void)hipFree(c->mov[k]);
-    void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->in_off, c->cursor,
+    void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->cursor,
                        c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
                        c->scan_tmp, c->flags, c->src, c->stage64, c->fieldbuf[0],
                        c->fieldbuf[1]};
@@ -135,7 +135,10 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
 
     c->C = p.C;
     c->cap = d.capacity;
-    c->slots = d.capacity + std::max<int64_t>(d.capacity / 4, (int64_t)st::kSlackMin * p.C);
+    // spare slots: a quarter of the capacity (at least kSlackMin per chunk),
+    // plus what rounding every room up to kAlign can take
+    c->slots = d.capacity + std::max<int64_t>(d.capacity / 4, (int64_t)st::kSlackMin * p.C) +
+               (int64_t)st::kAlign * p.C;
     c->mcap = std::max<int64_t>(std::min<int64_t>(d.capacity, 1 << 16), d.capacity / 8);
     c->max_items = p.C + (d.capacity + st::kSeg - 1) / st::kSeg;
     if (c->slots >= ((int64_t)1 << 31) - 1 || c->max_items >= ((int64_t)1 << 30))
@@ -166,13 +169,12 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     for (int k = 7; k < 10; ++k) A(&c->mov[k], (size_t)c->mcap * 4);
     A(&c->out_cnt, (size_t)C * 4);
     A(&c->in_cnt, (size_t)C * 4);
-    A(&c->in_off, (size_t)(C + 1) * 4);
     A(&c->cursor, (size_t)C * 4);
     A(&c->new_cnt, (size_t)C * 4);
     A(&c->nbase, (size_t)(C + 1) * 8);
     A(&c->nroom, (size_t)C * 4);
     A(&c->hole, (size_t)c->slots * 4);
-    A(&c->inbox, (size_t)c->mcap * 4);
+    A(&c->inbox, (size_t)c->slots * 4);
     A(&c->items, (size_t)c->max_items * 8);
     A(&c->nseg, (size_t)(C + 1) * 4);
     A(&c->scan_tmp, (size_t)(C / 1024 + 4) * 8);

@@ -2,7 +2,7 @@
 //
 // One step of the particle method (paper Sec. 2.1 equations of motion and
 // momentum source, Sec. 2.5 interpolation, deposit and time integration)
-// runs as:
+// is seven launches:
 //   step      one workgroup per work item (a run of at most kSeg particles of
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
@@ -11,14 +11,18 @@
 //             global reservation per workgroup, and flush the accumulator
 //             with one read-modify-write (or one atomic, for chunks split
 //             over several items) per cell;
-//   scan      arrival offsets per chunk, and the room check;
-//   inbox     movers grouped by destination chunk;
-//   fill      per chunk: arrivals and, when the chunk shrank, its tail
-//             particles fill the vacated slots, keeping the chunk dense;
-//   rekey     only when a chunk ran out of room, the mover list overflowed
+//   check     the room check of every chunk (a mover files itself in its
+//             destination chunk's inbox when it is emitted);
+//   fill      one wave per chunk: arrivals and, when the chunk shrank, its
+//             tail particles fill the vacated slots, keeping the chunk dense
+//             (or, when a full re-bin is due, the re-keyed counts);
+//   rooms, scatter, commit
+//             only when a chunk ran out of room, the mover list overflowed
 //             or particles were injected: a full counting-sort re-bin into
 //             the second store, copied back (decided on the device);
 //   items     work items of the next step, and the reset of the counters.
+// Device flags that decide between the two re-bins hold the tag (epoch) of
+// the step that raised them, so nothing has to clear them between steps.
 #include "st_internal.h"
 
 #include <math.h>
@@ -26,16 +30,26 @@
 namespace st {
 namespace {
 
-constexpr int kScanBlock = 1024;    // elements per block of the multi-block scan
 constexpr int kScan1Max = 1 << 16;  // largest scan done by one workgroup
+constexpr int kScanBlock = 1024;    // elements per block of the multi-block scan
 
 enum Gate { G_ALWAYS = 0, G_FULL = 1, G_MOVERS = 2 };
 
-__device__ __forceinline__ bool gate_open(const int32_t *flags, int gate)
+__device__ __forceinline__ bool full_rebin(const int32_t *flags, int32_t epoch)
+{
+    return flags[F_OVERFLOW] == epoch || flags[F_FORCE] == epoch;
+}
+
+__device__ __forceinline__ bool gate_open(const int32_t *flags, int gate, int32_t epoch)
 {
     if (gate == G_ALWAYS) return true;
-    const bool full = (flags[F_OVERFLOW] | flags[F_FORCE]) != 0;
-    return gate == G_FULL ? full : !full;
+    return (gate == G_FULL) == full_rebin(flags, epoch);
+}
+
+// movers of the step tagged `epoch` are counted in one of two slots
+__host__ __device__ __forceinline__ int nmov_slot(int32_t epoch)
+{
+    return (epoch & 1) ? F_NMOV_ODD : F_NMOV;
 }
 
 __device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
@@ -44,134 +58,168 @@ __device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
     return r < 0 ? r + n : r;
 }
 
+__device__ __forceinline__ uint64_t lanes_below_mask() { return (1ull << __lane_id()) - 1ull; }
+
 template <class V>
-__device__ V block_excl_scan(V v, V *sh, V &total)
+__device__ __forceinline__ V wave_incl_scan(V x)
 {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        V add = (t >= off) ? sh[t - off] : V(0);
-        __syncthreads();
-        sh[t] += add;
-        __syncthreads();
+    const int lane = __lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        const V y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
-    total = sh[blockDim.x - 1];
-    V excl = sh[t] - v;
+    return x;
+}
+
+// Block-wide exclusive scan of one value per thread (any multiple of 64
+// threads up to 1024); returns the prefix and the block total.
+template <class V>
+__device__ V block_excl_scan(V v, V &total)
+{
+    __shared__ V ws[16];
+    const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const V incl = wave_incl_scan(v);
+    if (lane == 63) ws[wave] = incl;
     __syncthreads();
-    return excl;
+    if (wave == 0) {
+        V w = lane < nw ? ws[lane] : V(0);
+        w = wave_incl_scan(w);
+        if (lane < nw) ws[lane] = w;
+    }
+    __syncthreads();
+    total = ws[nw - 1];
+    const V ex = (wave ? ws[wave - 1] : V(0)) + incl - v;
+    __syncthreads();
+    return ex;
 }
 
 // ---------------------------------------------------------------------------
 // exclusive scans of f(i), i < n: out[i] = sum_{j<i} f(j), out[n] = total
 // ---------------------------------------------------------------------------
+
+// whole scan in one workgroup of 1024 threads, 4096 elements per round
+template <class TO, class F>
+__device__ void block_scan_all(const F &f, int64_t n, TO *out)
+{
+    TO carry = 0;
+    for (int64_t r0 = 0; r0 < n; r0 += 4096) {
+        TO v[4];
+        TO s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = r0 + 4 * (int64_t)threadIdx.x + k;
+            v[k] = i < n ? f(i) : TO(0);
+            s += v[k];
+        }
+        TO total;
+        TO ex = carry + block_excl_scan<TO>(s, total);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = r0 + 4 * (int64_t)threadIdx.x + k;
+            if (i < n) out[i] = ex;
+            ex += v[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 template <class TO, class F>
 __global__ void __launch_bounds__(1024) k_scan1(F f, int64_t n, TO *out, const int32_t *flags,
-                                                int gate)
+                                                int gate, int32_t epoch)
 {
-    if (!gate_open(flags, gate)) return;
-    __shared__ TO sh[1024];
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t i0 = (int64_t)threadIdx.x * per;
-    const int64_t i1 = min(i0 + per, n);
-    TO s = 0;
-    for (int64_t i = i0; i < i1; ++i) s += f(i);
-    TO tot;
-    TO ex = block_excl_scan<TO>(s, sh, tot);
-    for (int64_t i = i0; i < i1; ++i) {
-        out[i] = ex;
-        ex += f(i);
-    }
-    if (threadIdx.x == 0) out[n] = tot;
+    if (!gate_open(flags, gate, epoch)) return;
+    block_scan_all<TO>(f, n, out);
 }
 
 template <class TO, class F>
 __global__ void __launch_bounds__(256) k_scan_partials(F f, int64_t n, TO *part,
-                                                       const int32_t *flags, int gate)
+                                                       const int32_t *flags, int gate,
+                                                       int32_t epoch)
 {
-    if (!gate_open(flags, gate)) return;
-    __shared__ TO sh[256];
-    int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    if (!gate_open(flags, gate, epoch)) return;
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
     TO s = 0;
     for (int k = 0; k < kScanBlock / 256; ++k) {
-        int64_t i = b0 + k * 256 + threadIdx.x;
+        const int64_t i = b0 + k * 256 + threadIdx.x;
         if (i < n) s += f(i);
     }
     TO tot;
-    block_excl_scan<TO>(s, sh, tot);
+    block_excl_scan<TO>(s, tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
 template <class TO>
-__global__ void __launch_bounds__(256) k_scan_spine(TO *part, int64_t nb, const int32_t *flags,
-                                                    int gate)
+__global__ void __launch_bounds__(1024) k_scan_spine(TO *part, int64_t nb, const int32_t *flags,
+                                                     int gate, int32_t epoch)
 {
-    if (!gate_open(flags, gate)) return;
-    __shared__ TO sh[256];
+    if (!gate_open(flags, gate, epoch)) return;
+    struct Id {
+        const TO *p;
+        __device__ TO operator()(int64_t i) const { return p[i]; }
+    };
+    // in place: the spine is short (n / 1024 entries)
     TO carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
-        int64_t i = b0 + threadIdx.x;
-        TO v = i < nb ? part[i] : TO(0);
-        TO tot;
-        TO ex = block_excl_scan<TO>(v, sh, tot);
+    for (int64_t r0 = 0; r0 < nb; r0 += 1024) {
+        const int64_t i = r0 + threadIdx.x;
+        const TO v = i < nb ? part[i] : TO(0);
+        TO total;
+        const TO ex = block_excl_scan<TO>(v, total);
         if (i < nb) part[i] = carry + ex;
-        carry += tot;
-        __syncthreads();
+        carry += total;
     }
 }
 
 template <class TO, class F>
 __global__ void __launch_bounds__(256) k_scan_final(F f, int64_t n, const TO *part, TO *out,
-                                                    const int32_t *flags, int gate)
+                                                    const int32_t *flags, int gate, int32_t epoch)
 {
-    if (!gate_open(flags, gate)) return;
-    __shared__ TO sh[256];
-    int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    if (!gate_open(flags, gate, epoch)) return;
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
     constexpr int K = kScanBlock / 256;
     TO v[K];
     TO s = 0;
     for (int k = 0; k < K; ++k) {
-        int64_t i = b0 + (int64_t)threadIdx.x * K + k;
+        const int64_t i = b0 + (int64_t)threadIdx.x * K + k;
         v[k] = i < n ? f(i) : TO(0);
         s += v[k];
     }
     TO tot;
-    TO ex = block_excl_scan<TO>(s, sh, tot) + part[blockIdx.x];
+    TO ex = block_excl_scan<TO>(s, tot) + part[blockIdx.x];
     for (int k = 0; k < K; ++k) {
-        int64_t i = b0 + (int64_t)threadIdx.x * K + k;
+        const int64_t i = b0 + (int64_t)threadIdx.x * K + k;
         if (i < n) out[i] = ex;
         ex += v[k];
         if (i == n - 1) out[n] = ex;
     }
 }
 
+// multi-block scan (three launches), for n > kScan1Max
 template <class TO, class F>
-hipError_t scan(F f, int64_t n, TO *out, TO *part, const int32_t *flags, int gate, hipStream_t s)
+hipError_t scan_multi(F f, int64_t n, TO *out, TO *part, const int32_t *flags, int gate,
+                      int32_t epoch, hipStream_t s)
 {
-    if (n <= kScan1Max) {
-        hipLaunchKernelGGL((k_scan1<TO, F>), dim3(1), dim3(1024), 0, s, f, n, out, flags, gate);
-        return hipGetLastError();
-    }
-    int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL((k_scan_partials<TO, F>), dim3(nb), dim3(256), 0, s, f, n, part, flags,
-                       gate);
-    hipLaunchKernelGGL((k_scan_spine<TO>), dim3(1), dim3(256), 0, s, part, nb, flags, gate);
+                       gate, epoch);
+    hipLaunchKernelGGL((k_scan_spine<TO>), dim3(1), dim3(1024), 0, s, part, nb, flags, gate,
+                       epoch);
     hipLaunchKernelGGL((k_scan_final<TO, F>), dim3(nb), dim3(256), 0, s, f, n, part, out, flags,
-                       gate);
+                       gate, epoch);
     return hipGetLastError();
 }
 
-// arrivals per chunk; also flags a chunk whose new count exceeds its room
-struct ArrivalsCheck {
-    const int32_t *in, *out, *cnt, *room;
-    int32_t *flags;
-    __device__ int32_t operator()(int64_t i) const
-    {
-        const int32_t a = in[i];
-        if ((int64_t)cnt[i] - out[i] + a > room[i]) flags[F_OVERFLOW] = 1;
-        return a;
+template <class TO, class F>
+hipError_t scan(F f, int64_t n, TO *out, TO *part, const int32_t *flags, int gate, int32_t epoch,
+                hipStream_t s)
+{
+    if (n <= kScan1Max) {
+        hipLaunchKernelGGL((k_scan1<TO, F>), dim3(1), dim3(1024), 0, s, f, n, out, flags, gate,
+                           epoch);
+        return hipGetLastError();
     }
-};
+    return scan_multi<TO>(f, n, out, part, flags, gate, epoch, s);
+}
 
 // work items per chunk
 struct Segments {
@@ -180,7 +228,8 @@ struct Segments {
 };
 
 // rooms of a re-binned layout: the spare slots are shared out in proportion
-// to (count + kSlackMin); also records the room
+// to (count + kSlackMin), rounded down to whole groups of kAlign slots, on
+// top of the count rounded up to kAlign; also records the room
 struct Rooms {
     const int32_t *new_cnt;
     int64_t spare, denom;
@@ -188,7 +237,8 @@ struct Rooms {
     __device__ int64_t operator()(int64_t i) const
     {
         const int64_t n = new_cnt[i];
-        const int64_t r = n + (denom > 0 ? spare * (n + kSlackMin) / denom : 0);
+        const int64_t extra = denom > 0 ? spare * (n + kSlackMin) / denom : 0;
+        const int64_t r = (n + kAlign - 1) / kAlign * kAlign + extra / kAlign * kAlign;
         nroom[i] = (int32_t)r;
         return r;
     }
@@ -231,30 +281,52 @@ __device__ __forceinline__ int64_t chunk_after(const Params &p, int64_t c, T &ox
 }
 
 // ---------------------------------------------------------------------------
-// work items and the per-step reset
+// work items of the next step, and the reset of the per-step counters
 // ---------------------------------------------------------------------------
-__global__ void k_items(const int32_t *noff, int64_t C, int32_t *items, int32_t *out_cnt,
-                        int32_t *in_cnt, int32_t *new_cnt, int32_t *cursor, int32_t *flags)
+struct ItemArgs {
+    int64_t C;
+    int32_t *noff;       // [C+1] exclusive scan of the items per chunk
+    int32_t *items;
+    int32_t *out_cnt, *in_cnt, *new_cnt, *cursor;
+    int32_t *flags;
+    int32_t epoch;
+};
+
+__device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
 {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t o = noff[c], e = noff[c + 1];
-        for (int32_t s = 0; s < e - o; ++s) {
-            items[2 * (int64_t)(o + s)] = (int32_t)c;
-            items[2 * (int64_t)(o + s) + 1] = s;
-        }
-        out_cnt[c] = 0;
-        in_cnt[c] = 0;
-        new_cnt[c] = 0;
-        cursor[c] = 0;
-        if (c == C - 1) flags[F_NITEMS] = e;
+    const int32_t o = a.noff[c], e = a.noff[c + 1];
+    for (int32_t s = 0; s < e - o; ++s) {
+        a.items[2 * (int64_t)(o + s)] = (int32_t)c;
+        a.items[2 * (int64_t)(o + s) + 1] = s;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        flags[F_OVERFLOW] = 0;
-        flags[F_FORCE] = 0;
-        flags[F_LASTMOV] = flags[F_NMOV];  // movers of the step just finished
-        flags[F_NMOV] = 0;
-    }
+    a.out_cnt[c] = 0;
+    a.in_cnt[c] = 0;
+    a.new_cnt[c] = 0;
+    a.cursor[c] = 0;
+}
+
+__device__ __forceinline__ void finish_flags(const ItemArgs &a)
+{
+    a.flags[F_NITEMS] = a.noff[a.C];
+    a.flags[F_LASTMOV] = a.flags[nmov_slot(a.epoch)];
+    a.flags[nmov_slot(a.epoch + 1)] = 0;
+}
+
+// one workgroup: scan, items and reset (C <= kScan1Max)
+__global__ void __launch_bounds__(1024) k_items1(Segments f, ItemArgs a)
+{
+    block_scan_all<int32_t>(f, a.C, a.noff);
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x) write_items(a, c);
+    if (threadIdx.x == 0) finish_flags(a);
+}
+
+__global__ void k_items(ItemArgs a)
+{
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.C;
+         c += (int64_t)gridDim.x * blockDim.x)
+        write_items(a, c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) finish_flags(a);
 }
 
 __global__ void k_set_flag(int32_t *flags, int which, int32_t v) { flags[which] = v; }
@@ -275,9 +347,11 @@ struct StepArgs {
     int32_t *out_cnt;
     int32_t *in_cnt;
     int32_t *hole;
+    int32_t *inbox;          // arrivals of chunk c at inbox[base[c] + rank]
     int32_t *flags;
     int64_t grid;            // launched workgroups (for the XCD remap)
     int32_t deposit;         // 0: move and re-bin only (tape recompute)
+    int32_t epoch;           // tag of this step in the device flags
     Params p;
     T dt;
     T dt_h[3];               // dt / h per axis
@@ -296,32 +370,52 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t grid)
     return x * per + (x < rem ? x : rem) + k;
 }
 
+// G consecutive values at a G*sizeof(T)-aligned address
+template <class T, int G>
+__device__ __forceinline__ void vld(const T *p, T (&v)[G])
+{
+    const T *q = (const T *)__builtin_assume_aligned(p, G * sizeof(T));
+    __builtin_memcpy(v, q, G * sizeof(T));
+}
+
+template <class T, int G>
+__device__ __forceinline__ void vst(T *p, const T (&v)[G])
+{
+    T *q = (T *)__builtin_assume_aligned(p, G * sizeof(T));
+    __builtin_memcpy(q, v, G * sizeof(T));
+}
+
 // A mover already written in place (un-rebased offsets, relative to chunk
-// c): records the vacated slot, marks it, and copies the particle, re-based
-// onto its destination chunk, into the mover list at m.
+// c): records the vacated slot, marks it, copies the particle, re-based
+// onto its destination chunk, into the mover list at m and files m in the
+// destination's inbox.
 template <class T, class A>
 __device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, int64_t base,
                                            int64_t q, int64_t m, int64_t hpos)
 {
     const View<T> &V = a.V;
     T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-    const int64_t cn = chunk_after(a.p, c, x, y, z);
+    const T vx = V.vx[q], vy = V.vy[q], vz = V.vz[q], dd = V.d[q];
     const int32_t id = V.id[q];
+    const int64_t cn = chunk_after(a.p, c, x, y, z);
     V.id[q] = -1 - id;
     a.hole[base + hpos] = (int32_t)(q - base);
     if (m < a.mcap) {
         a.mv.ox[m] = x;
         a.mv.oy[m] = y;
         a.mv.oz[m] = z;
-        a.mv.vx[m] = V.vx[q];
-        a.mv.vy[m] = V.vy[q];
-        a.mv.vz[m] = V.vz[q];
-        a.mv.d[m] = V.d[q];
+        a.mv.vx[m] = vx;
+        a.mv.vy[m] = vy;
+        a.mv.vz[m] = vz;
+        a.mv.d[m] = dd;
         a.mv.id[m] = id;
         a.mv.dest[m] = (int32_t)cn;
-        a.mv.rank[m] = atomicAdd(&a.in_cnt[cn], 1);
+        const int32_t r = atomicAdd(&a.in_cnt[cn], 1);
+        // an arrival rank beyond the room means the chunk overflows (the room
+        // check after the step sees it too); it is then never read
+        if (r < V.room[cn]) a.inbox[V.base[cn] + r] = (int32_t)m;
     } else {
-        a.flags[F_OVERFLOW] = 1;
+        a.flags[F_OVERFLOW] = a.epoch;
     }
 }
 
@@ -331,6 +425,8 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     constexpr int S = E + 2;            // tile edge with the halo
     constexpr int S3 = S * S * S;
     constexpr int E3 = E * E * E;
+    constexpr int G = 16 / sizeof(T);   // consecutive particles per thread
+    static_assert(kAlign % G == 0, "chunk rooms must hold whole particle groups");
     __shared__ T tile[3 * S3];
     __shared__ A acc[3 * E3];
     __shared__ int32_t mslot[kMoverStage];
@@ -347,32 +443,41 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     const int64_t s1 = min(s0 + (int64_t)kSeg, base + (int64_t)cnt);
     const bool multi = cnt > kSeg;
     const Params &p = a.p;
-    const int64_t cx = c % p.nc[0];
-    const int64_t cy = (c / p.nc[0]) % p.nc[1];
-    const int64_t cz = c / ((int64_t)p.nc[0] * p.nc[1]);
+    const int cx = (int)(c % p.nc[0]);
+    const int cy = (int)((c / p.nc[0]) % p.nc[1]);
+    const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
     const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
 
-    // first particle of this thread, loaded while the tile is staged
-    int64_t q = s0 + threadIdx.x;
-    bool have = q < s1;
-    T nx = 0, ny = 0, nz = 0, nvx = 0, nvy = 0, nvz = 0, nd = 0;
-    if (have) {
-        nx = V.ox[q]; ny = V.oy[q]; nz = V.oz[q];
-        nvx = V.vx[q]; nvy = V.vy[q]; nvz = V.vz[q];
-        nd = V.d[q];
-    }
-
-    // stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped
-    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
-        const int comp = t / S3;
-        const int r = t - comp * S3;
-        const int k = r / (S * S);
-        const int j = (r / S) % S;
-        const int i = r % S;
-        const int64_t gx = wrapi(cx * E - 1 + i, p.n[0]);
-        const int64_t gy = wrapi(cy * E - 1 + j, p.n[1]);
-        const int64_t gz = wrapi(cz * E - 1 + k, p.n[2]);
-        tile[t] = a.u[comp * ncell + (gz * p.n[1] + gy) * p.n[0] + gx];
+    // stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped; all
+    // of a thread's loads are issued before the first is used
+    {
+        constexpr int NT = (3 * S3 + kBlock - 1) / kBlock;
+        T vals[NT];
+        const int ox0 = cx * E - 1, oy0 = cy * E - 1, oz0 = cz * E - 1;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int t = threadIdx.x + u * kBlock;
+            if (t < 3 * S3) {
+                const int comp = t / S3;
+                const int r = t - comp * S3;
+                const int k = r / (S * S);
+                const int j = (r / S) % S;
+                const int i = r % S;
+                int gx = ox0 + i, gy = oy0 + j, gz = oz0 + k;
+                gx += gx < 0 ? p.n[0] : 0;
+                gx -= gx >= p.n[0] ? p.n[0] : 0;
+                gy += gy < 0 ? p.n[1] : 0;
+                gy -= gy >= p.n[1] ? p.n[1] : 0;
+                gz += gz < 0 ? p.n[2] : 0;
+                gz -= gz >= p.n[2] ? p.n[2] : 0;
+                vals[u] = a.u[comp * ncell + ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int t = threadIdx.x + u * kBlock;
+            if (t < 3 * S3) tile[t] = vals[u];
+        }
     }
     for (int t = threadIdx.x; t < 3 * E3; t += kBlock) acc[t] = A(0);
     if (threadIdx.x == 0) mcount = 0;
@@ -382,97 +487,117 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     const A inv_V = (A)p.inv_V;
     const A dtA = (A)dt;
     const T fe = T(E), inv_e = T(1) / T(E);
-    while (have) {
-        const T xi[3] = {nx, ny, nz};
-        const T up[3] = {nvx, nvy, nvz};
-        const T dp = nd;
-        const int64_t qc = q;
-        q += kBlock;
-        have = q < s1;
-        if (have) {  // prefetch the next particle of this thread
-            nx = V.ox[q]; ny = V.oy[q]; nz = V.oz[q];
-            nvx = V.vx[q]; nvy = V.vy[q]; nvz = V.vz[q];
-            nd = V.d[q];
-        }
+    // groups of G consecutive slots; s0 is a multiple of G (chunk bases and
+    // kSeg are), and a group that runs past s1 stays inside the chunk's room
+    const int64_t ngroups = (s1 - s0 + G - 1) / G;
+    for (int64_t gi = threadIdx.x; gi < ngroups; gi += kBlock) {
+        const int64_t q0 = s0 + gi * G;
+        T X[G], Y[G], Z[G], UX[G], UY[G], UZ[G], DD[G];
+        vld<T, G>(V.ox + q0, X);
+        vld<T, G>(V.oy + q0, Y);
+        vld<T, G>(V.oz + q0, Z);
+        vld<T, G>(V.vx + q0, UX);
+        vld<T, G>(V.vy + q0, UY);
+        vld<T, G>(V.vz + q0, UZ);
+        vld<T, G>(V.d + q0, DD);
+        uint32_t movers = 0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const bool valid = q0 + k < s1;
+            const T xi[3] = {X[k], Y[k], Z[k]};
+            const T up[3] = {UX[k], UY[k], UZ[k]};
+            const T dp = DD[k];
 
-        // gather the fluid velocity at the particle
-        T uf[3];
-        int cl[3];
-        if (INTERP == 0) {
-            T f[3];
-            int i0[3];
+            // gather the fluid velocity at the particle
+            T uf[3];
+            int cl[3];
+            if (INTERP == 0) {
+                T f[3];
+                int i0[3];
+                for (int ax = 0; ax < 3; ++ax) {
+                    const T s = xi[ax] - T(0.5);
+                    const T fl = floor(s);
+                    // -1 .. E-1 for offsets in [0, E); clamped so that no
+                    // state can index outside the tile
+                    i0[ax] = min(max((int)fl, -1), E - 1);
+                    f[ax] = s - fl;
+                    cl[ax] = min(max((int)xi[ax], 0), E - 1);
+                }
+                const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
+                const T wx0 = T(1) - f[0], wx1 = f[0];
+                const T wy0 = T(1) - f[1], wy1 = f[1];
+                const T wz0 = T(1) - f[2], wz1 = f[2];
+                const T w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
+                for (int comp = 0; comp < 3; ++comp) {
+                    const T *tc = tile + comp * S3 + t0;
+                    const T r00 = wx0 * tc[0] + wx1 * tc[1];
+                    const T r10 = wx0 * tc[S] + wx1 * tc[S + 1];
+                    const T r01 = wx0 * tc[S * S] + wx1 * tc[S * S + 1];
+                    const T r11 = wx0 * tc[S * S + S] + wx1 * tc[S * S + S + 1];
+                    uf[comp] = w00 * r00 + w10 * r10 + w01 * r01 + w11 * r11;
+                }
+            } else {
+                for (int ax = 0; ax < 3; ++ax) cl[ax] = min(max((int)xi[ax], 0), E - 1);
+                const int t0 = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
+                for (int comp = 0; comp < 3; ++comp) uf[comp] = tile[comp * S3 + t0];
+            }
+
+            // semi-implicit Euler, drag implicit and gravity explicit:
+            //   u_p' = (tau u_p + dt u_f + tau dt g) / (tau + dt)
+            // written as the velocity change, which keeps its relative
+            // accuracy in binary32:  u_p' - u_p = dt (u_f - u_p + tau g) / (tau + dt)
+            const T tau = a.tau_coef * dp * dp;
+            const T rD = dt / (tau + dt);
+            T upn[3], xn[3];
             for (int ax = 0; ax < 3; ++ax) {
-                const T s = xi[ax] - T(0.5);
-                const T fl = floor(s);
-                // -1 .. E-1 for offsets in [0, E); clamped so that no state
-                // can index outside the tile
-                i0[ax] = min(max((int)fl, -1), E - 1);
-                f[ax] = s - fl;
-                cl[ax] = min(max((int)xi[ax], 0), E - 1);
+                upn[ax] = up[ax] + rD * ((uf[ax] - up[ax]) + tau * a.g[ax]);
+                xn[ax] = xi[ax] + upn[ax] * a.dt_h[ax];
             }
-            const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
-            const T wx0 = T(1) - f[0], wx1 = f[0];
-            const T wy0 = T(1) - f[1], wy1 = f[1];
-            const T wz0 = T(1) - f[2], wz1 = f[2];
-            const T w00 = wy0 * wz0, w10 = wy1 * wz0, w01 = wy0 * wz1, w11 = wy1 * wz1;
-            for (int comp = 0; comp < 3; ++comp) {
-                const T *tc = tile + comp * S3 + t0;
-                const T r00 = wx0 * tc[0] + wx1 * tc[1];
-                const T r10 = wx0 * tc[S] + wx1 * tc[S + 1];
-                const T r01 = wx0 * tc[S * S] + wx1 * tc[S * S + 1];
-                const T r11 = wx0 * tc[S * S + S] + wx1 * tc[S * S + S + 1];
-                uf[comp] = w00 * r00 + w10 * r10 + w01 * r01 + w11 * r11;
+
+            // drag impulse J = m (u_p' - u_p - g dt) = m dt (u_f - u_p - g dt) / (tau + dt),
+            // in the accumulator precision from the stored inputs; the fluid
+            // receives -J / V in the start-of-step cell
+            if (a.deposit && valid) {
+                const A dA = (A)dp;
+                const A mass = (A)p.mass_coef * dA * dA * dA;
+                const A tauA = (A)p.tau_coef * dA * dA;
+                const A coef = -mass * dtA / (tauA + dtA) * inv_V;
+                const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+                for (int ax = 0; ax < 3; ++ax) {
+                    const A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
+                    atomicAdd(&acc[ax * E3 + cell], coef * slip);
+                }
             }
-        } else {
-            for (int ax = 0; ax < 3; ++ax) cl[ax] = min(max((int)xi[ax], 0), E - 1);
-            const int t0 = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
-            for (int comp = 0; comp < 3; ++comp) uf[comp] = tile[comp * S3 + t0];
-        }
 
-        // semi-implicit Euler, drag implicit and gravity explicit:
-        //   u_p' = (tau u_p + dt u_f + tau dt g) / (tau + dt)
-        // written as the velocity change, which keeps its relative accuracy
-        // in binary32:  u_p' - u_p = dt (u_f - u_p + tau g) / (tau + dt)
-        const T tau = a.tau_coef * dp * dp;
-        const T rD = dt / (tau + dt);
-        T upn[3], xn[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            upn[ax] = up[ax] + rD * ((uf[ax] - up[ax]) + tau * a.g[ax]);
-            xn[ax] = xi[ax] + upn[ax] * a.dt_h[ax];
+            // relocate: stayers keep re-based offsets; movers keep un-rebased
+            // ones (relative to this chunk) until they are emitted
+            T xr[3] = {xn[0], xn[1], xn[2]};
+            const int kx = rebase(xr[0], fe, inv_e);
+            const int ky = rebase(xr[1], fe, inv_e);
+            const int kz = rebase(xr[2], fe, inv_e);
+            const bool mover = (kx | ky | kz) != 0;
+            X[k] = mover ? xn[0] : xr[0];
+            Y[k] = mover ? xn[1] : xr[1];
+            Z[k] = mover ? xn[2] : xr[2];
+            UX[k] = upn[0];
+            UY[k] = upn[1];
+            UZ[k] = upn[2];
+            if (valid && mover) movers |= 1u << k;
         }
-
-        // drag impulse J = m (u_p' - u_p - g dt) = m dt (u_f - u_p - g dt) / (tau + dt),
-        // in the accumulator precision from the stored inputs; the fluid
-        // receives -J / V in the start-of-step cell
-        if (a.deposit) {
-            const A dA = (A)dp;
-            const A mass = (A)p.mass_coef * dA * dA * dA;
-            const A tauA = (A)p.tau_coef * dA * dA;
-            const A coef = -mass * dtA / (tauA + dtA) * inv_V;
-            const int cell = (cl[2] * E + cl[1]) * E + cl[0];
-            for (int ax = 0; ax < 3; ++ax) {
-                const A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
-                atomicAdd(&acc[ax * E3 + cell], coef * slip);
-            }
-        }
-
-        // relocate: stayers keep re-based offsets; movers keep un-rebased
-        // ones (relative to this chunk) until they are emitted
-        T xr[3] = {xn[0], xn[1], xn[2]};
-        const int kx = rebase(xr[0], fe, inv_e);
-        const int ky = rebase(xr[1], fe, inv_e);
-        const int kz = rebase(xr[2], fe, inv_e);
-        const bool mover = (kx | ky | kz) != 0;
-        V.ox[qc] = mover ? xn[0] : xr[0];
-        V.oy[qc] = mover ? xn[1] : xr[1];
-        V.oz[qc] = mover ? xn[2] : xr[2];
-        V.vx[qc] = upn[0];
-        V.vy[qc] = upn[1];
-        V.vz[qc] = upn[2];
-        if (mover) {
-            const int k = atomicAdd(&mcount, 1);
-            if (k < kMoverStage) {
-                mslot[k] = (int32_t)(qc - base);
+        // slots past s1 in the last group are dead; writing them is harmless
+        vst<T, G>(V.ox + q0, X);
+        vst<T, G>(V.oy + q0, Y);
+        vst<T, G>(V.oz + q0, Z);
+        vst<T, G>(V.vx + q0, UX);
+        vst<T, G>(V.vy + q0, UY);
+        vst<T, G>(V.vz + q0, UZ);
+        while (movers) {
+            const int k = __ffs(movers) - 1;
+            movers &= movers - 1;
+            const int64_t qc = q0 + k;
+            const int j = atomicAdd(&mcount, 1);
+            if (j < kMoverStage) {
+                mslot[j] = (int32_t)(qc - base);
             } else {  // more movers than the LDS stage holds: emit directly
                 const int64_t m = atomicAdd(a.nmov, 1);
                 const int64_t h = atomicAdd(&a.out_cnt[c], 1);
@@ -482,14 +607,26 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     }
     __syncthreads();
 
-    // flush the chunk's accumulated source
+    // flush the chunk's accumulated source (loads batched before the stores)
     if (a.deposit) {
+        constexpr int NF = (3 * E3 + kBlock - 1) / kBlock;
         A *dst = a.src + c * (3 * E3);
-        for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
-            const A v = acc[t];
-            if (v != A(0)) {
-                if (multi) atomicAdd(dst + t, v);
-                else dst[t] += v;
+        if (multi) {
+            for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
+                const A v = acc[t];
+                if (v != A(0)) atomicAdd(dst + t, v);
+            }
+        } else {
+            A old[NF];
+#pragma unroll
+            for (int u = 0; u < NF; ++u) {
+                const int t = threadIdx.x + u * kBlock;
+                old[u] = t < 3 * E3 ? dst[t] : A(0);
+            }
+#pragma unroll
+            for (int u = 0; u < NF; ++u) {
+                const int t = threadIdx.x + u * kBlock;
+                if (t < 3 * E3) dst[t] = old[u] + acc[t];
             }
         }
     }
@@ -507,20 +644,22 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     }
 }
 
-// ---------------------------------------------------------------------------
-// mover-only re-bin
-// ---------------------------------------------------------------------------
+// room check after the step: a chunk whose new count exceeds its room
+// forces the full re-bin
 template <class T>
-__global__ void k_inbox(const Movers<T> mv, const int32_t *nmov, int64_t mcap,
-                        const int32_t *in_off, int32_t *inbox, const int32_t *flags)
+__global__ void k_check(View<T> V, int64_t C, const int32_t *out_cnt, const int32_t *in_cnt,
+                        int32_t *flags, int32_t epoch)
 {
-    if (!gate_open(flags, G_MOVERS)) return;
-    const int64_t n = min((int64_t)*nmov, mcap);
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < n;
-         m += (int64_t)gridDim.x * blockDim.x)
-        inbox[in_off[mv.dest[m]] + mv.rank[m]] = (int32_t)m;
+    bool bad = false;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x)
+        bad |= (int64_t)V.cnt[c] - out_cnt[c] + in_cnt[c] > V.room[c];
+    if (__ballot(bad) != 0 && __lane_id() == 0) flags[F_OVERFLOW] = epoch;
 }
 
+// ---------------------------------------------------------------------------
+// re-bin after the step: the mover-only fill or the full counting sort
+// ---------------------------------------------------------------------------
 template <class T>
 __device__ __forceinline__ void copy_slot(const View<T> &V, int64_t dst, int64_t src)
 {
@@ -549,122 +688,137 @@ __device__ __forceinline__ void place_mover(const View<T> &V, int64_t dst, const
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_fill(View<T> V, int64_t C, const int32_t *out_cnt,
-                                              const int32_t *in_cnt, const int32_t *in_off,
-                                              const int32_t *inbox, const Movers<T> mv,
-                                              int32_t *hole, const int32_t *flags)
+struct RebinArgs {
+    View<T> V;
+    View<T> W;               // second store (target of the full re-bin)
+    Movers<T> mv;
+    int64_t C;
+    const int32_t *out_cnt, *in_cnt, *inbox;
+    int32_t *hole;
+    const int32_t *items, *nitems;
+    Params p;
+    int64_t npend;           // staged injected particles (full re-bin only)
+    int32_t *new_cnt, *cursor;
+    const int64_t *nbase;
+    const int32_t *nroom;
+    int64_t slots;
+    int32_t *flags;
+    int32_t epoch;
+};
+
+// One wave per chunk: the arrivals, and when the chunk shrank its live tail
+// particles, fill the vacated slots below the new count.
+template <class T>
+__device__ void fill_chunks(const RebinArgs<T> &a)
 {
-    if (!gate_open(flags, G_MOVERS)) return;
-    __shared__ int32_t sh[256];
-    for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
-        const int32_t out = out_cnt[c], in = in_cnt[c];
+    const View<T> &V = a.V;
+    const int lane = __lane_id();
+    const int64_t wpb = blockDim.x >> 6;
+    for (int64_t c = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); c < a.C;
+         c += (int64_t)gridDim.x * wpb) {
+        const int32_t out = a.out_cnt[c], in = a.in_cnt[c];
         if (out == 0 && in == 0) continue;
         const int64_t base = V.base[c];
         const int32_t cnt = V.cnt[c];
         const int32_t ncnt = cnt - out + in;
-        int32_t *H = hole + base;            // chunk-relative vacated slots
-        const int32_t *box = inbox + in_off[c];
+        int32_t *H = a.hole + base;            // chunk-relative vacated slots
+        const int32_t *box = a.inbox + base;   // arrivals, by rank
         if (ncnt >= cnt) {
             // every vacated slot lies below the new count: arrivals fill
             // them first, then extend the chunk
-            for (int32_t r = threadIdx.x; r < in; r += blockDim.x) {
-                const int64_t dst = base + (r < out ? H[r] : cnt + (r - out));
-                place_mover(V, dst, mv, box[r]);
-            }
+            for (int32_t r = lane; r < in; r += 64)
+                place_mover(V, base + (r < out ? H[r] : cnt + (r - out)), a.mv, box[r]);
         } else {
-            // keep the vacated slots below the new count (compacted in place)
+            // keep the vacated slots below the new count, compacted in place
+            // (a round only writes below the entries it has already read)
             int32_t k = 0;
-            for (int32_t j0 = 0; j0 < out; j0 += blockDim.x) {
-                const int32_t j = j0 + threadIdx.x;
+            for (int32_t j0 = 0; j0 < out; j0 += 64) {
+                const int32_t j = j0 + lane;
                 const int32_t h = j < out ? H[j] : 0;
-                const int32_t keep = (j < out && h < ncnt) ? 1 : 0;
-                int32_t tot;
-                const int32_t ex = block_excl_scan<int32_t>(keep, sh, tot);
-                if (keep) H[k + ex] = h;
-                k += tot;
-                __syncthreads();
+                const bool keep = j < out && h < ncnt;
+                const uint64_t mask = __ballot(keep);
+                if (keep) H[k + __popcll(mask & lanes_below_mask())] = h;
+                k += __popcll(mask);
             }
+            __threadfence_block();
             // arrivals take the first `in` of them
-            for (int32_t r = threadIdx.x; r < in; r += blockDim.x)
-                place_mover(V, base + H[r], mv, box[r]);
+            for (int32_t r = lane; r < in; r += 64) place_mover(V, base + H[r], a.mv, box[r]);
             // live particles beyond the new count take the rest
             int32_t placed = 0;
             const int32_t tail = cnt - ncnt;
-            for (int32_t t0 = 0; t0 < tail; t0 += blockDim.x) {
-                const int32_t t = t0 + threadIdx.x;
+            for (int32_t t0 = 0; t0 < tail; t0 += 64) {
+                const int32_t t = t0 + lane;
                 const int64_t slot = base + ncnt + t;
-                const int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
-                int32_t tot;
-                const int32_t ex = block_excl_scan<int32_t>(live, sh, tot);
-                if (live) copy_slot(V, base + H[in + placed + ex], slot);
-                placed += tot;
-                __syncthreads();
+                const bool live = t < tail && V.id[slot] >= 0;
+                const uint64_t mask = __ballot(live);
+                if (live) copy_slot(V, base + H[in + placed + __popcll(mask & lanes_below_mask())], slot);
+                placed += __popcll(mask);
             }
         }
-        if (threadIdx.x == 0) V.cnt[c] = ncnt;
-        __syncthreads();
+        if (lane == 0) V.cnt[c] = ncnt;
     }
 }
 
-// ---------------------------------------------------------------------------
-// full re-bin: counting sort into the second store, then copied back
-// ---------------------------------------------------------------------------
+// Full re-bin, first pass: particles per destination chunk.
 template <class T>
-__global__ void __launch_bounds__(256) k_rekey_count(View<T> V, const int32_t *items,
-                                                     const int32_t *nitems, Params p,
-                                                     const Movers<T> mv, int64_t npend,
-                                                     int32_t *new_cnt, const int32_t *flags)
+__device__ void rekey_count(const RebinArgs<T> &a)
 {
-    if (!gate_open(flags, G_FULL)) return;
-    const int64_t ni = *nitems;
+    const View<T> &V = a.V;
+    const int64_t ni = *a.nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
-        const int64_t c = items[2 * it], seg = items[2 * it + 1];
+        const int64_t c = a.items[2 * it], seg = a.items[2 * it + 1];
         const int64_t s0 = V.base[c] + seg * kSeg;
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            const int64_t cn = chunk_after(p, c, x, y, z);
+            const int64_t cn = chunk_after(a.p, c, x, y, z);
             // one atomic per wave for the lanes that stay in chunk c
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
                 if (__lane_id() == __ffsll((unsigned long long)stay) - 1)
-                    atomicAdd(&new_cnt[c], __popcll(stay));
+                    atomicAdd(&a.new_cnt[c], __popcll(stay));
             } else {
-                atomicAdd(&new_cnt[cn], 1);
+                atomicAdd(&a.new_cnt[cn], 1);
             }
         }
     }
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < a.npend;
          m += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&new_cnt[mv.dest[m]], 1);
+        atomicAdd(&a.new_cnt[a.mv.dest[m]], 1);
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_rekey_scatter(View<T> V, View<T> W, const int32_t *items,
-                                                       const int32_t *nitems, Params p,
-                                                       const Movers<T> mv, int64_t npend,
-                                                       const int64_t *nbase, int32_t *cursor,
-                                                       const int32_t *flags)
+__global__ void __launch_bounds__(256) k_fill_or_count(RebinArgs<T> a)
 {
-    if (!gate_open(flags, G_FULL)) return;
-    const int64_t ni = *nitems;
+    if (full_rebin(a.flags, a.epoch)) rekey_count(a);
+    else fill_chunks(a);
+}
+
+// Full re-bin, second pass: scatter into the second store.
+template <class T>
+__global__ void __launch_bounds__(256) k_rekey_scatter(RebinArgs<T> a)
+{
+    if (!full_rebin(a.flags, a.epoch)) return;
+    const View<T> &V = a.V;
+    const View<T> &W = a.W;
+    const int64_t ni = *a.nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
-        const int64_t c = items[2 * it], seg = items[2 * it + 1];
+        const int64_t c = a.items[2 * it], seg = a.items[2 * it + 1];
         const int64_t s0 = V.base[c] + seg * kSeg;
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            const int64_t cn = chunk_after(p, c, x, y, z);
+            const int64_t cn = chunk_after(a.p, c, x, y, z);
             int64_t dst;
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
                 const int leader = __ffsll((unsigned long long)stay) - 1;
                 int32_t b = 0;
-                if (__lane_id() == leader) b = atomicAdd(&cursor[c], __popcll(stay));
+                if (__lane_id() == leader) b = atomicAdd(&a.cursor[c], __popcll(stay));
                 b = __shfl(b, leader);
-                dst = nbase[c] + b + __popcll(stay & ((1ull << __lane_id()) - 1ull));
+                dst = a.nbase[c] + b + __popcll(stay & lanes_below_mask());
             } else {
-                dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
+                dst = a.nbase[cn] + atomicAdd(&a.cursor[cn], 1);
             }
             W.ox[dst] = x;
             W.oy[dst] = y;
@@ -677,30 +831,31 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(View<T> V, View<T> W, con
             W.id[dst] = id < 0 ? -1 - id : id;
         }
     }
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < npend;
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < a.npend;
          m += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t cn = mv.dest[m];
-        const int64_t dst = nbase[cn] + atomicAdd(&cursor[cn], 1);
-        W.ox[dst] = mv.ox[m];
-        W.oy[dst] = mv.oy[m];
-        W.oz[dst] = mv.oz[m];
-        W.vx[dst] = mv.vx[m];
-        W.vy[dst] = mv.vy[m];
-        W.vz[dst] = mv.vz[m];
-        W.d[dst] = mv.d[m];
-        W.id[dst] = mv.id[m];
+        const int64_t cn = a.mv.dest[m];
+        const int64_t dst = a.nbase[cn] + atomicAdd(&a.cursor[cn], 1);
+        W.ox[dst] = a.mv.ox[m];
+        W.oy[dst] = a.mv.oy[m];
+        W.oz[dst] = a.mv.oz[m];
+        W.vx[dst] = a.mv.vx[m];
+        W.vy[dst] = a.mv.vy[m];
+        W.vz[dst] = a.mv.vz[m];
+        W.d[dst] = a.mv.d[m];
+        W.id[dst] = a.mv.id[m];
     }
 }
 
+// Full re-bin, last pass: the second store and the new layout become the store.
 template <class T>
-__global__ void k_rekey_commit(View<T> V, View<T> W, int64_t slots, int64_t C,
-                               const int32_t *new_cnt, const int64_t *nbase,
-                               const int32_t *nroom, int32_t *flags)
+__global__ void k_rekey_commit(RebinArgs<T> a)
 {
-    if (!gate_open(flags, G_FULL)) return;
+    if (!full_rebin(a.flags, a.epoch)) return;
+    const View<T> &V = a.V;
+    const View<T> &W = a.W;
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t gs = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t q = g0; q < slots; q += gs) {
+    for (int64_t q = g0; q < a.slots; q += gs) {
         V.ox[q] = W.ox[q];
         V.oy[q] = W.oy[q];
         V.oz[q] = W.oz[q];
@@ -710,12 +865,12 @@ __global__ void k_rekey_commit(View<T> V, View<T> W, int64_t slots, int64_t C,
         V.d[q] = W.d[q];
         V.id[q] = W.id[q];
     }
-    for (int64_t c = g0; c < C; c += gs) {
-        V.cnt[c] = new_cnt[c];
-        V.base[c] = nbase[c];
-        V.room[c] = nroom[c];
+    for (int64_t c = g0; c < a.C; c += gs) {
+        V.cnt[c] = a.new_cnt[c];
+        V.base[c] = a.nbase[c];
+        V.room[c] = a.nroom[c];
     }
-    if (g0 == 0) flags[F_REPACKS] += 1;
+    if (g0 == 0) a.flags[F_REPACKS] += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -958,25 +1113,54 @@ hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
                               : launch_step_t<T, A, E, 0>(c, a, s);
 }
 
-// the full re-bin, gated on the device (overflow or force flag)
 template <class T>
-hipError_t launch_rekey(st_ctx *c, int64_t npend, hipStream_t s)
+RebinArgs<T> rebin_args(st_ctx *c, int64_t npend)
 {
-    const View<T> V = view_of<T>(c, 0), W = view_of<T>(c, 1);
-    const Movers<T> mv = movers_of<T>(c);
+    RebinArgs<T> a;
+    a.V = view_of<T>(c, 0);
+    a.W = view_of<T>(c, 1);
+    a.mv = movers_of<T>(c);
+    a.C = c->C;
+    a.out_cnt = c->out_cnt;
+    a.in_cnt = c->in_cnt;
+    a.inbox = c->inbox;
+    a.hole = c->hole;
+    a.items = c->items;
+    a.nitems = c->flags + F_NITEMS;
+    a.p = c->prm;
+    a.npend = npend;
+    a.new_cnt = c->new_cnt;
+    a.cursor = c->cursor;
+    a.nbase = c->nbase;
+    a.nroom = c->nroom;
+    a.slots = c->slots;
+    a.flags = c->flags;
+    a.epoch = c->epoch;
+    return a;
+}
+
+// everything after the step kernel: fill or full re-bin, then the items
+template <class T>
+hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
+{
+    const RebinArgs<T> a = rebin_args<T>(c, npend);
     const int64_t C = c->C;
-    const int64_t gi = c->max_items < 65536 ? c->max_items : 65536;
+    int64_t g = (C + 3) / 4;                      // one wave per chunk in the fill
+    const int64_t gi = c->max_items;              // one block per item in the count
+    if (gi > g) g = gi;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(256), 0, s, a);
     const int64_t total = c->count + npend;
-    hipLaunchKernelGGL((k_rekey_count<T>), dim3(gi), dim3(256), 0, s, V, c->items,
-                       c->flags + F_NITEMS, c->prm, mv, npend, c->new_cnt, c->flags);
-    Rooms rooms{c->new_cnt, c->slots - total, total + (int64_t)kSlackMin * C, c->nroom};
-    hipError_t e = scan<int64_t>(rooms, C, c->nbase, c->scan_tmp, c->flags, G_FULL, s);
+    Rooms rooms{c->new_cnt, c->slots - total - (int64_t)kAlign * C,
+                total + (int64_t)kSlackMin * C, c->nroom};
+    hipError_t e = scan<int64_t>(rooms, C, c->nbase, c->scan_tmp, c->flags, G_FULL, c->epoch, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gi), dim3(256), 0, s, V, W, c->items,
-                       c->flags + F_NITEMS, c->prm, mv, npend, c->nbase, c->cursor, c->flags);
-    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, V,
-                       W, c->slots, C, c->new_cnt, c->nbase, c->nroom, c->flags);
-    return hipGetLastError();
+    const int64_t gs = c->max_items < 65536 ? c->max_items : 65536;
+    hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_items(c, s);
 }
 
 }  // namespace
@@ -986,11 +1170,16 @@ hipError_t launch_rekey(st_ctx *c, int64_t npend, hipStream_t s)
 // ---------------------------------------------------------------------------
 hipError_t launch_items(st_ctx *c, hipStream_t s)
 {
-    hipError_t e = scan<int32_t>(Segments{c->cnt}, c->C, c->nseg, (int32_t *)c->scan_tmp,
-                                 c->flags, G_ALWAYS, s);
+    ItemArgs a{c->C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
+               c->epoch};
+    if (c->C <= kScan1Max) {
+        hipLaunchKernelGGL(k_items1, dim3(1), dim3(1024), 0, s, Segments{c->cnt}, a);
+        return hipGetLastError();
+    }
+    hipError_t e = scan_multi<int32_t>(Segments{c->cnt}, c->C, c->nseg, (int32_t *)c->scan_tmp,
+                                       c->flags, G_ALWAYS, c->epoch, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_items, dim3(grid_for(c->C)), dim3(256), 0, s, c->nseg, c->C, c->items,
-                       c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags);
+    hipLaunchKernelGGL(k_items, dim3(grid_for(c->C)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1008,6 +1197,7 @@ hipError_t launch_init(st_ctx *c, hipStream_t s)
 
 hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStream_t s)
 {
+    c->epoch += 1;
     return dispatch(c, [&](auto t, auto acc) -> hipError_t {
         using T = decltype(t);
         using A = decltype(acc);
@@ -1018,14 +1208,16 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         a.u = (const T *)u;
         a.src = (A *)c->src;
         a.mv = movers_of<T>(c);
-        a.nmov = c->flags + F_NMOV;
+        a.nmov = c->flags + nmov_slot(c->epoch);
         a.mcap = c->mcap;
         a.out_cnt = c->out_cnt;
         a.in_cnt = c->in_cnt;
         a.hole = c->hole;
+        a.inbox = c->inbox;
         a.flags = c->flags;
         a.grid = c->max_items;
         a.deposit = deposit;
+        a.epoch = c->epoch;
         a.p = c->prm;
         a.dt = (T)dt;
         for (int ax = 0; ax < 3; ++ax) {
@@ -1052,35 +1244,22 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         if (r == hipSuccess && c->timing) r = hipEventRecord(ev[1], s);
         if (r != hipSuccess) return r;
 
-        // mover-only re-bin (gated off on the device when a full re-bin is due)
-        const View<T> V = a.V;
-        const Movers<T> mv = a.mv;
-        const int64_t C = c->C;
-        ArrivalsCheck chk{c->in_cnt, c->out_cnt, c->cnt, c->room, c->flags};
-        r = scan<int32_t>(chk, C, c->in_off, (int32_t *)c->scan_tmp, c->flags, G_ALWAYS, s);
-        if (r != hipSuccess) return r;
-        hipLaunchKernelGGL((k_inbox<T>), dim3(grid_for(c->mcap, 2048)), dim3(256), 0, s, mv,
-                           c->flags + F_NMOV, c->mcap, c->in_off, c->inbox, c->flags);
-        const int64_t gf = C < 65536 ? C : 65536;
-        hipLaunchKernelGGL((k_fill<T>), dim3(gf), dim3(256), 0, s, V, C, c->out_cnt, c->in_cnt,
-                           c->in_off, c->inbox, mv, c->hole, c->flags);
+        hipLaunchKernelGGL((k_check<T>), dim3(grid_for(c->C, 1024)), dim3(256), 0, s, a.V, c->C,
+                           c->out_cnt, c->in_cnt, c->flags, c->epoch);
         r = hipGetLastError();
         if (r != hipSuccess) return r;
-        r = launch_rekey<T>(c, 0, s);
-        if (r != hipSuccess) return r;
-        return launch_items(c, s);
+        return launch_rebin<T>(c, 0, s);
     });
 }
 
 hipError_t launch_flush_pending(st_ctx *c, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->flags, (int)F_FORCE, 1);
-    hipError_t e = dispatch(c, [&](auto t, auto) -> hipError_t {
+    c->epoch += 1;
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(1), 0, s, c->flags, (int)F_FORCE, c->epoch);
+    return dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
-        return launch_rekey<T>(c, c->pending, s);
+        return launch_rebin<T>(c, c->pending, s);
     });
-    if (e != hipSuccess) return e;
-    return launch_items(c, s);
 }
 
 hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,

@@ -24,6 +24,7 @@ constexpr int kBlock = 256;       // threads per workgroup of the step kernels
 constexpr int kSeg = 16384;       // max particles per step work item
 constexpr int kSlackMin = 32;     // spare-slot weight per chunk in the room formula
 constexpr int kMoverStage = 512;  // movers per workgroup staged in LDS
+constexpr int kAlign = 4;         // chunk rooms are whole multiples of this
 
 template <class T>
 struct View {
@@ -61,9 +62,11 @@ struct Params {
     double mass_coef;      // w rho_p pi / 6:    m = mass_coef d^3
 };
 
-// Flags and counters on the device (one int32 each).
+// Flags and counters on the device (one int32 each).  F_OVERFLOW and
+// F_FORCE hold the tag (epoch) of the step or flush that raised them; the
+// movers of a step are counted in F_NMOV or F_NMOV_ODD by the tag's parity.
 enum DevFlag { F_OVERFLOW = 0, F_NMOV = 1, F_NITEMS = 2, F_FORCE = 3, F_BADINPUT = 4,
-               F_REPACKS = 5, F_LASTMOV = 6, F_COUNT = 8 };
+               F_REPACKS = 5, F_LASTMOV = 6, F_NMOV_ODD = 7, F_COUNT = 8 };
 
 struct TapeStep {
     const void *u;     // field of the step (borrowed)
@@ -92,6 +95,7 @@ struct st_ctx {
     int64_t count = 0;         // particles in the store (host mirror)
     int64_t pending = 0;       // injected particles waiting in the staging area
     int64_t next_id = 0;
+    int32_t epoch = 0;         // tag of the last step or flush launched
 
     // device memory
     void *store[2][8] = {};    // SoA arrays: [0] the store, [1] re-bin target
@@ -100,13 +104,12 @@ struct st_ctx {
     int32_t *cnt = nullptr;    // [C]
     void *mov[10] = {};        // Movers arrays
     int32_t *out_cnt = nullptr, *in_cnt = nullptr;
-    int32_t *in_off = nullptr;     // [C+1]
     int32_t *cursor = nullptr;     // [C] scatter cursors of the full re-bin
     int32_t *new_cnt = nullptr;    // [C]
     int64_t *nbase = nullptr;      // [C+1] first slots of the re-binned layout
     int32_t *nroom = nullptr;      // [C]   rooms of the re-binned layout
     int32_t *hole = nullptr;       // [slots]
-    int32_t *inbox = nullptr;      // [mcap]
+    int32_t *inbox = nullptr;      // [slots] arrivals of chunk c at base[c] + rank
     int32_t *items = nullptr;      // [max_items][2]
     int32_t *nseg = nullptr;       // [C+1] offsets of the work items per chunk
     int64_t *scan_tmp = nullptr;   // block partials of the scans
