@@ -1,12 +1,355 @@
-// Adjoint of the particle step (reverse mode), filled in below.
+// Reverse mode of the taped particle steps (the paper gives no adjoint; this
+// is the derivative of the discrete step the library computes).
+//
+// For a loss L whose derivative with respect to the time-integrated source
+// is lambda = dL/dSu_int, one step of one particle (state x, u_p, d at the
+// step start; u_p' the new velocity; D = tau + dt) is reversed as
+//   Jbar   = -lambda[c0] / V_cell                  (deposit -> gather)
+//   wbar   = ubar' + dt xbar' + m Jbar              (everything reading u_p')
+//   ubar   = -m Jbar + (tau / D) wbar
+//   mbar   = Jbar . (u_p' - u_p - g dt)
+//   ufbar  = (dt / D) wbar                           (interpolation -> scatter)
+//   taubar = wbar . (u_p + dt g - u_p') / D
+//   Ubar[corner k] += w_k ufbar,   xbar = xbar' + sum_k grad w_k (U_k . ufbar)
+//   dbar  += taubar 2 tau / d + mbar 3 m / d
+// The cell c0 and the periodic wrap are piecewise constant (zero derivative).
+//
+// Checkpoints of the particle store are kept every `tape_every` taped steps;
+// each segment is recomputed from its checkpoint (deposit off), saving the
+// store and its layout before every step, and then reversed newest first.
+// The per-particle adjoint state is kept by particle id, so the re-binning
+// between steps needs no special treatment.
 #include "st_internal.h"
 
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
 namespace st {
+namespace {
+
+template <class T>
+struct AdjArgs {
+    // saved store of the step (pointers into a snapshot)
+    const T *ox, *oy, *oz, *vx, *vy, *vz, *d;
+    const int32_t *id;
+    const int64_t *base;
+    const int32_t *cnt;
+    const int32_t *items;
+    const int32_t *nitems;
+    int64_t grid;
+    const T *u;              // field of the step [3][n2][n1][n0]
+    const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
+    double *xb, *ub, *db;    // adjoint state by id ([P][3], [P][3], [P])
+    double *Ubar;            // dL/du [3][n2][n1][n0]
+    int64_t count;
+    Params p;
+    double dt;
+};
+
+template <class T, int E, int INTERP>
+__global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
+{
+    constexpr int S = E + 2;
+    constexpr int S3 = S * S * S;
+    constexpr int E3 = E * E * E;
+    __shared__ T tile[3 * S3];
+    __shared__ double ubt[3 * S3];   // Ubar over the tile
+
+    const int64_t item = blockIdx.x;
+    if (item >= *a.nitems) return;
+    const Params &p = a.p;
+    const int64_t c = a.items[2 * item], seg = a.items[2 * item + 1];
+    const int64_t s0 = a.base[c] + seg * kSeg;
+    const int64_t s1 = min(s0 + (int64_t)kSeg, a.base[c] + (int64_t)a.cnt[c]);
+    const int cx = (int)(c % p.nc[0]);
+    const int cy = (int)((c / p.nc[0]) % p.nc[1]);
+    const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
+    const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    const int ox0 = cx * E - 1, oy0 = cy * E - 1, oz0 = cz * E - 1;
+
+    auto tile_cell = [&](int r) -> int64_t {  // field index of tile cell r
+        const int k = r / (S * S), j = (r / S) % S, i = r % S;
+        int gx = ox0 + i, gy = oy0 + j, gz = oz0 + k;
+        gx += gx < 0 ? p.n[0] : 0;
+        gx -= gx >= p.n[0] ? p.n[0] : 0;
+        gy += gy < 0 ? p.n[1] : 0;
+        gy -= gy >= p.n[1] ? p.n[1] : 0;
+        gz += gz < 0 ? p.n[2] : 0;
+        gz -= gz >= p.n[2] ? p.n[2] : 0;
+        return ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx;
+    };
+    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
+        const int comp = t / S3;
+        tile[t] = a.u[comp * ncell + tile_cell(t - comp * S3)];
+        ubt[t] = 0.0;
+    }
+    __syncthreads();
+
+    const double dt = a.dt;
+    const double inv_V = p.inv_V;
+    const double *lam = a.lamC + c * 3 * E3;
+    for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock) {
+        const int64_t id = a.id[q];
+        if (id < 0 || id >= a.count) continue;  // never in a saved store
+        const double xi[3] = {(double)a.ox[q], (double)a.oy[q], (double)a.oz[q]};
+        const double up[3] = {(double)a.vx[q], (double)a.vy[q], (double)a.vz[q]};
+        const double dp = (double)a.d[q];
+
+        // interpolation stencil in binary64 at the saved position
+        int cl[3], i0[3];
+        double om[3][2], dom[3][2];
+        for (int ax = 0; ax < 3; ++ax) {
+            cl[ax] = min(max((int)xi[ax], 0), E - 1);
+            if (INTERP == 0) {
+                const double s = xi[ax] - 0.5;
+                const double fl = floor(s);
+                i0[ax] = min(max((int)fl, -1), E - 1);
+                const double f = s - fl;
+                om[ax][0] = 1.0 - f;
+                om[ax][1] = f;
+                dom[ax][0] = -p.inv_h[ax];
+                dom[ax][1] = p.inv_h[ax];
+            }
+        }
+        double uf[3] = {0.0, 0.0, 0.0};
+        int tc[8];
+        double w[8];
+        int nk;
+        if (INTERP == 0) {
+            nk = 8;
+            const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
+            for (int k = 0; k < 8; ++k) {
+                const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+                tc[k] = t0 + (bz * S + by) * S + bx;
+                w[k] = om[0][bx] * om[1][by] * om[2][bz];
+            }
+        } else {
+            nk = 1;
+            tc[0] = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
+            w[0] = 1.0;
+        }
+        for (int k = 0; k < nk; ++k)
+            for (int comp = 0; comp < 3; ++comp) uf[comp] += w[k] * (double)tile[comp * S3 + tc[k]];
+
+        // forward quantities of the step
+        const double tau = p.tau_coef * dp * dp;
+        const double mass = p.mass_coef * dp * dp * dp;
+        const double D = tau + dt;
+        double upn[3];
+        for (int ax = 0; ax < 3; ++ax)
+            upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) / D;
+
+        // reverse
+        const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+        double xb[3], ub[3], ufb[3];
+        double mbar = 0.0, taubar = 0.0;
+        for (int ax = 0; ax < 3; ++ax) {
+            xb[ax] = a.xb[3 * id + ax];
+            ub[ax] = a.ub[3 * id + ax];
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            const double Jbar = -lam[ax * E3 + cell] * inv_V;
+            const double wbar = ub[ax] + dt * xb[ax] + mass * Jbar;
+            mbar += Jbar * (upn[ax] - up[ax] - p.g[ax] * dt);
+            ufb[ax] = dt / D * wbar;
+            taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]) / D;
+            ub[ax] = -mass * Jbar + tau / D * wbar;
+        }
+        for (int k = 0; k < nk; ++k) {
+            double dot = 0.0;
+            for (int comp = 0; comp < 3; ++comp) {
+                atomicAdd(&ubt[comp * S3 + tc[k]], w[k] * ufb[comp]);
+                dot += (double)tile[comp * S3 + tc[k]] * ufb[comp];
+            }
+            if (INTERP == 0) {
+                const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+                xb[0] += dom[0][bx] * om[1][by] * om[2][bz] * dot;
+                xb[1] += om[0][bx] * dom[1][by] * om[2][bz] * dot;
+                xb[2] += om[0][bx] * om[1][by] * dom[2][bz] * dot;
+            }
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            a.xb[3 * id + ax] = xb[ax];
+            a.ub[3 * id + ax] = ub[ax];
+        }
+        a.db[id] += taubar * 2.0 * tau / dp + mbar * 3.0 * mass / dp;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
+        const double v = ubt[t];
+        if (v != 0.0) {
+            const int comp = t / S3;
+            atomicAdd(a.Ubar + comp * ncell + tile_cell(t - comp * S3), v);
+        }
+    }
+}
+
+// dL/dSu_int from the field layout into the chunk layout
+__global__ void k_lambda_to_chunks(const double *lam, Params p, double *lamC)
+{
+    const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2];
+    const int64_t ncell = nx * ny * nz;
+    const int E = p.E;
+    const int64_t E3 = (int64_t)E * E * E;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < 3 * ncell;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t comp = t / ncell, r = t - comp * ncell;
+        const int64_t i = r % nx, j = (r / nx) % ny, k = r / (nx * ny);
+        const int64_t c = ((k / E) * p.nc[1] + (j / E)) * p.nc[0] + (i / E);
+        const int64_t l = ((k % E) * E + (j % E)) * E + (i % E);
+        lamC[c * 3 * E3 + comp * E3 + l] = lam[t];
+    }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+inline int64_t grid_of(int64_t n)
+{
+    const int64_t g = (n + 255) / 256;
+    return g < 1 ? 1 : (g > 16384 ? 16384 : g);
+}
+
+template <class T>
+AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
+                    double *xb, double *ub, double *db, double *Ubar)
+{
+    const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
+    const T *st = reinterpret_cast<const T *>(snap + L.state);
+    AdjArgs<T> a;
+    a.ox = st;
+    a.oy = st + c->slots;
+    a.oz = st + 2 * c->slots;
+    a.vx = st + 3 * c->slots;
+    a.vy = st + 4 * c->slots;
+    a.vz = st + 5 * c->slots;
+    a.d = st + 6 * c->slots;
+    a.id = reinterpret_cast<const int32_t *>(snap + L.id);
+    a.base = reinterpret_cast<const int64_t *>(snap + L.base);
+    a.cnt = reinterpret_cast<const int32_t *>(snap + L.cnt);
+    a.items = reinterpret_cast<const int32_t *>(snap + L.items);
+    a.nitems = reinterpret_cast<const int32_t *>(snap + L.nitems);
+    a.grid = c->max_items;
+    a.u = reinterpret_cast<const T *>(ts.u);
+    a.lamC = lamC;
+    a.xb = xb;
+    a.ub = ub;
+    a.db = db;
+    a.Ubar = Ubar;
+    a.count = c->count;
+    a.p = c->prm;
+    a.dt = ts.dt;
+    return a;
+}
+
+template <class T>
+hipError_t launch_adjoint_step(st_ctx *c, const AdjArgs<T> &a, hipStream_t s)
+{
+    const dim3 g(c->max_items), b(kBlock);
+    const bool ngp = c->prm.interp == 1;
+    switch (c->prm.E) {
+    case 2:
+        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 2, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<T, 2, 0>), g, b, 0, s, a);
+        break;
+    case 4:
+        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 4, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<T, 4, 0>), g, b, 0, s, a);
+        break;
+    default:
+        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 8, 1>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_step<T, 8, 0>), g, b, 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { (void)hipFree(p); }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
+};
+
+}  // namespace
 
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s)
 {
-    (void)c; (void)lam; (void)dU; (void)dd; (void)s;
-    return hipErrorNotSupported;
+    const int64_t ntape = (int64_t)c->tape.size();
+    const int64_t K = c->tape_every;
+    const int64_t nseg = (int64_t)c->snaps.size();
+    if (ntape == 0 || K <= 0 || nseg != (ntape + K - 1) / K) return hipErrorInvalidValue;
+    const int64_t P = c->count;
+    const int64_t ncell = (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+    const int64_t E3 = (int64_t)c->prm.E * c->prm.E * c->prm.E;
+    const size_t sbytes = snapshot_bytes(c);
+
+    DevBuf final_state, lamC, xb, ub, db;
+    std::vector<DevBuf> steps((size_t)K);
+    hipError_t e = final_state.alloc(sbytes);
+    if (e == hipSuccess) e = lamC.alloc((size_t)c->C * 3 * E3 * 8);
+    if (e == hipSuccess) e = xb.alloc((size_t)P * 24);
+    if (e == hipSuccess) e = ub.alloc((size_t)P * 24);
+    if (e == hipSuccess) e = db.alloc((size_t)P * 8);
+    for (int64_t k = 0; k < K && e == hipSuccess; ++k) e = steps[(size_t)k].alloc(sbytes);
+    if (e != hipSuccess) return e;
+
+    // temporaries are freed on return: an error return first drains the stream
+    auto fail = [&](hipError_t err) {
+        (void)hipStreamSynchronize(s);
+        return err;
+    };
+    // keep the state the forward run ended in
+    e = launch_snapshot(c, final_state.p, 0, s);
+    if (e != hipSuccess) return fail(e);
+    hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
+                       (double *)lamC.p);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * P)), dim3(256), 0, s, (double *)xb.p, 3 * P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * P)), dim3(256), 0, s, (double *)ub.p, 3 * P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(P)), dim3(256), 0, s, (double *)db.p, P);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(e);
+
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        const int64_t k0 = sg * K, k1 = std::min(k0 + K, ntape);
+        e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
+        if (e != hipSuccess) return fail(e);
+        // recompute the segment, saving the store before every step
+        for (int64_t k = k0; k < k1; ++k) {
+            e = launch_snapshot(c, steps[(size_t)(k - k0)].p, 0, s);
+            if (e == hipSuccess && k + 1 < k1)
+                e = launch_step(c, c->tape[(size_t)k].u, c->tape[(size_t)k].dt, 0, s);
+            if (e != hipSuccess) return fail(e);
+        }
+        // and reverse it, newest step first
+        for (int64_t k = k1 - 1; k >= k0; --k) {
+            const char *snap = (const char *)steps[(size_t)(k - k0)].p;
+            if (c->form == ST_FORM_FP64)
+                e = launch_adjoint_step<double>(
+                    c, adj_args<double>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
+                                        (double *)xb.p, (double *)ub.p, (double *)db.p, dU), s);
+            else
+                e = launch_adjoint_step<float>(
+                    c, adj_args<float>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
+                                       (double *)xb.p, (double *)ub.p, (double *)db.p, dU), s);
+            if (e != hipSuccess) return fail(e);
+        }
+    }
+    e = hipMemcpyAsync(dd, db.p, (size_t)P * 8, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return fail(e);
+    e = launch_snapshot(c, final_state.p, 1, s);
+    if (e != hipSuccess) return fail(e);
+    // the temporaries are freed when this returns: finish first
+    return hipStreamSynchronize(s);
 }
 
 }  // namespace st

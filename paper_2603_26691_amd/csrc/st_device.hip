@@ -1011,16 +1011,25 @@ __global__ void k_rotate(const T *u0, T *u, int64_t ncell, double cs, double sn)
 
 // checkpoint copy of the store (all slots) and its layout
 template <class T>
-__global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, int restore)
+__global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, SnapLayout L,
+                           int32_t *items, const int32_t *nitems, int64_t max_items, int restore)
 {
     T *arr[7] = {V.ox, V.oy, V.oz, V.vx, V.vy, V.vz, V.d};
-    T *sT = reinterpret_cast<T *>(buf);
-    int32_t *sid = reinterpret_cast<int32_t *>(sT + 7 * slots);
-    int64_t *sbase = reinterpret_cast<int64_t *>(
-        buf + (((7 * slots * sizeof(T) + slots * 4) + 7) & ~(size_t)7));
-    int32_t *sroom = reinterpret_cast<int32_t *>(sbase + C);
-    int32_t *scnt = sroom + C;
+    T *sT = reinterpret_cast<T *>(buf + L.state);
+    int32_t *sid = reinterpret_cast<int32_t *>(buf + L.id);
+    int64_t *sbase = reinterpret_cast<int64_t *>(buf + L.base);
+    int32_t *sroom = reinterpret_cast<int32_t *>(buf + L.room);
+    int32_t *scnt = reinterpret_cast<int32_t *>(buf + L.cnt);
+    int32_t *sitems = reinterpret_cast<int32_t *>(buf + L.items);
+    int32_t *snitems = reinterpret_cast<int32_t *>(buf + L.nitems);
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!restore) {  // the work items of this layout travel with it
+        const int64_t ni = *nitems;
+        for (int64_t k = g0; k < 2 * ni; k += (int64_t)gridDim.x * blockDim.x)
+            sitems[k] = items[k];
+        if (g0 == 0) *snitems = (int32_t)ni;
+    }
+    (void)max_items;
     const int64_t gs = (int64_t)gridDim.x * blockDim.x;
     for (int64_t q = g0; q < slots; q += gs) {
         if (restore) {
@@ -1328,18 +1337,23 @@ hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, 
 
 size_t snapshot_bytes(const st_ctx *c)
 {
-    const size_t head = (7 * (size_t)c->slots * c->tsize + (size_t)c->slots * 4 + 7) & ~(size_t)7;
-    return head + (size_t)c->C * 16;
+    return snap_layout(c->slots, c->tsize, c->C, c->max_items).bytes;
 }
 
+// Saves the store, its layout and its work items into dst, or (restore)
+// puts a saved store and layout back and rebuilds the work items.
 hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s)
 {
-    return dispatch(c, [&](auto t, auto) -> hipError_t {
+    const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
+    hipError_t e = dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
         hipLaunchKernelGGL((k_snapshot<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s,
-                           view_of<T>(c, 0), c->slots, c->C, (char *)dst, restore);
+                           view_of<T>(c, 0), c->slots, c->C, (char *)dst, L, c->items,
+                           c->flags + F_NITEMS, c->max_items, restore);
         return hipGetLastError();
     });
+    if (e != hipSuccess || !restore) return e;
+    return launch_items(c, s);
 }
 
 }  // namespace st

@@ -78,6 +78,28 @@ struct Snapshot {      // particle store and layout at a checkpoint
     size_t bytes = 0;
 };
 
+// Byte offsets inside a snapshot: the 7 state arrays ([7][slots] of the
+// state scalar), ids, the chunk layout (base, room, cnt) and the work items
+// of that layout with their count.
+struct SnapLayout {
+    size_t state, id, base, room, cnt, items, nitems, bytes;
+};
+
+inline SnapLayout snap_layout(int64_t slots, size_t tsize, int64_t C, int64_t max_items)
+{
+    auto up8 = [](size_t v) { return (v + 7) & ~(size_t)7; };
+    SnapLayout l;
+    l.state = 0;
+    l.id = 7 * (size_t)slots * tsize;
+    l.base = up8(l.id + (size_t)slots * 4);
+    l.room = l.base + (size_t)C * 8;
+    l.cnt = l.room + (size_t)C * 4;
+    l.items = up8(l.cnt + (size_t)C * 4);
+    l.nitems = l.items + (size_t)max_items * 8;
+    l.bytes = up8(l.nitems + 4);
+    return l;
+}
+
 }  // namespace st
 
 struct st_ctx {

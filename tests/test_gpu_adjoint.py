@@ -1,0 +1,170 @@
+"""GPU adjoint (st_backward) against the FP64 oracle adjoint and central
+finite differences of the GPU forward run.
+
+Loss: L = sum (S_int - T)^2 over the time-integrated source, T built from a
+run with the diameters scaled by 1.1; so dL/dS_int = 2 (S_int - T).
+Gradients are compared in relative L2 norm, 1e-4 for the FP32 chunk-local
+form (forward in binary32, adjoint in binary64) and near round-off for the
+FP64 form; FD samples whose per-step cells change between the +h and -h
+runs are excluded and counted.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import fields, oracle_mesh, state, tracker, workload
+from oracle.oracle import load as load_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return load_oracle()
+
+
+def _case(P=4000, n=(16, 16, 16), nsteps=30):
+    return workload("adj64", n=n, P=P, nsteps=nsteps, noise=0.2)
+
+
+def _forward(w, form, x, up, d, U, K):
+    import torch
+    t = tracker(w, form)
+    t.inject(x, up, d)
+    s0 = state(t)
+    for _ in range(w.nsteps):
+        t.step(U, w.dt, tape=K)
+    S = t.sources()
+    return t, s0, S
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _target(w, form, x, up, d, U):
+    t = tracker(w, form)
+    t.inject(x, up, d * 1.1)
+    for _ in range(w.nsteps):
+        t.step(U, w.dt)
+    T = t.sources().cpu().numpy()
+    t.close()
+    return T
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-9), ("fp32_local", 1e-4)])
+def test_adjoint_matches_oracle(orc, form, tol):
+    import torch
+    w = _case()
+    x, up, d = w.particles()
+    Udev, Uor = fields(w, form)
+    T = _target(w, form, x, up, d, Udev)
+    t, s0, S = _forward(w, form, x, up, d, Udev, K=7)
+    lam = 2.0 * (S.cpu().numpy() - T)
+    before = state(t)
+    dU, dd = t.backward(torch.from_numpy(lam).cuda())
+    after = state(t)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), f"state restored after backward: {k}"
+    dU, dd = dU.cpu().numpy(), dd.cpu().numpy()
+    # the oracle differentiates from the GPU's stored initial state
+    oU, od = orc.adjoint(oracle_mesh(w), Uor, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps, lam)
+    eU, ed = _rel(dU, oU), _rel(dd, od)
+    print(form, "adjoint rel L2: dU", eU, "dd", ed)
+    assert eU < tol and ed < tol
+    t.close()
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    import torch
+    w = _case(P=3000, nsteps=12)
+    x, up, d = w.particles()
+    Udev, _ = fields(w, "fp64")
+    lam = None
+    grads = []
+    for K in (1, 5, 12, 50):
+        t, _, S = _forward(w, "fp64", x, up, d, Udev, K)
+        if lam is None:
+            lam = torch.sin(S * 1e3).contiguous()
+        grads.append([g.cpu().numpy() for g in t.backward(lam)])
+        t.close()
+    for g in grads[1:]:
+        assert _rel(g[0], grads[0][0]) < 1e-12 and _rel(g[1], grads[0][1]) < 1e-12
+
+
+def test_adjoint_against_finite_differences():
+    """Central differences of the GPU's own FP64 forward (h = 1e-3 relative
+    for diameters, 1e-3 m/s for field entries) on 32 sampled entries."""
+    import torch
+    w = _case(P=2000, nsteps=10)
+    x, up, d = w.particles()
+    Udev, _ = fields(w, "fp64")
+    T = _target(w, "fp64", x, up, d, Udev)
+
+    def run(dd, U):
+        t = tracker(w, "fp64")
+        t.inject(x, up, dd)
+        cells = []
+        for _ in range(w.nsteps):
+            cells.append(state(t)["cell"])
+            t.step(U, w.dt)
+        S = t.sources().cpu().numpy()
+        t.close()
+        return float(np.sum((S - T) ** 2)), np.stack(cells)
+
+    t, _, S = _forward(w, "fp64", x, up, d, Udev, K=4)
+    lam = torch.from_numpy(2.0 * (S.cpu().numpy() - T)).cuda()
+    dU, dd = (g.cpu().numpy() for g in t.backward(lam))
+    t.close()
+    _, cells0 = run(d, Udev)
+    rng = np.random.default_rng(3)
+    checked = skipped = 0
+    for p in rng.choice(w.P, 16, replace=False):
+        h = 1e-3 * d[p]
+        dp_, dm_ = d.copy(), d.copy()
+        dp_[p] += h
+        dm_[p] -= h
+        Lp, cp = run(dp_, Udev)
+        Lm, cm = run(dm_, Udev)
+        if not (np.array_equal(cp, cells0) and np.array_equal(cm, cells0)):
+            skipped += 1
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - dd[p]) <= 2e-4 * abs(fd) + 1e-6 * np.abs(dd).max(), (p, fd, dd[p])
+        checked += 1
+    flat = np.argsort(-np.abs(dU).ravel())[:16]
+    for q in flat:
+        idx = np.unravel_index(q, dU.shape)
+        Up, Um = Udev.clone(), Udev.clone()
+        Up[idx] += 1e-3
+        Um[idx] -= 1e-3
+        Lp, cp = run(d, Up)
+        Lm, cm = run(d, Um)
+        if not (np.array_equal(cp, cells0) and np.array_equal(cm, cells0)):
+            skipped += 1
+            continue
+        fd = (Lp - Lm) / 2e-3
+        assert abs(fd - dU[idx]) <= 2e-4 * abs(fd) + 1e-6 * np.abs(dU).max(), (idx, fd, dU[idx])
+        checked += 1
+    print("FD checked", checked, "skipped", skipped)
+    assert checked >= 24
+
+
+def test_autograd_function():
+    import torch
+    import paper_2603_26691_amd as pkg
+    from paper_2603_26691_amd.autograd import Run
+    w = _case(P=2000, nsteps=8)
+    x, up, d = w.particles()
+    U = torch.from_numpy(w.field()).cuda().requires_grad_(True)
+    dd = torch.from_numpy(d).cuda().requires_grad_(True)
+    T = torch.from_numpy(_target(w, "fp32_local", x, up, d, U.detach().float())).cuda()
+    run = Run(tracker(w, "fp32_local"), x, up, w.dt, w.nsteps, tape_every=3)
+    S = pkg.DepositFn.apply(U, dd, run)
+    loss = ((S - T) ** 2).sum()
+    loss.backward()
+    t2, _, S2 = _forward(w, "fp32_local", x, up, d, U.detach().float().contiguous(), K=3)
+    gU, gd = (g.cpu().numpy() for g in t2.backward((2.0 * (S2 - T)).contiguous()))
+    assert _rel(U.grad.cpu().numpy(), gU) < 1e-12
+    assert _rel(dd.grad.cpu().numpy(), gd) < 1e-12
+    run.tracker.close()
+    t2.close()
