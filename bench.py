@@ -1,15 +1,18 @@
 """Benchmark of the per-particle time step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tg128] [--form fp32_local]
+                [--no-fp64] [--no-adjoint] [--no-scale] [--no-cpu]
 
 A step is one pass of the whole hot path (gather, integrate, deposit,
 relocate and re-bin) over every particle of the workload.  Inputs are
 seeded synthetic data resident in HBM before the timed region starts; K
 steps are timed with events on the stream the kernels run on, bracketed by
 device synchronisations.  Prints one JSON line with the whole-job
-particle-steps/s, the step kernel's roofline figures, the FP64 form on the
-same workload and the FP64 oracle timed on this host's cores on a bounded
-sample of the same workload.
+particle-steps/s, the step kernel's roofline figures, and beside them: the
+FP64 form on the same workload, forward+adjoint throughput (64^3, 1e6
+particles, checkpoints every 20 steps), the 1.4e9-particle 512^3 run with
+the field update on a second stream, and the FP64 oracle timed on this
+host's cores on a bounded sample of the workload.
 """
 import argparse
 import json
@@ -41,31 +44,55 @@ def make_tracker(pkg, w, form):
                        mu_f=w.mu_f, g=w.g, rho_p=w.rho_p, parcel_weight=w.parcel_weight)
 
 
-def inject_all(t, w):
+def inject_host(t, w):
     for b in range(w.n_batches()):
         x, up, d = w.batch(b)
         t.inject(x, up, d)
 
 
-def time_form(pkg, torch, np, w, form, steps, warmup):
-    t = make_tracker(pkg, w, form)
-    inject_all(t, w)
+def inject_device(t, w):
+    for b in range(w.n_device_batches()):
+        x, up, d = w.device_batch(b)
+        t.inject(x, up, d)
+        del x, up, d
+
+
+def field_of(torch, np, w, form):
     U = w.field()
-    U = torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
+    return torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
+
+
+def roofline(form, w, kernel_ms, launches, items):
+    bytes_launch, per_p, per_item = algorithmic_bytes(form, w.P, items, w.chunk_edge)
+    avg_s = kernel_ms / max(launches, 1) / 1e3
+    achieved = bytes_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_step",
+            "avg_kernel_ms": avg_s * 1e3, "bytes_per_launch": bytes_launch,
+            "model": f"{per_p} B/particle + {per_item} B/work item, {items} items"}
+
+
+def time_steps(torch, t, U, dt, steps, warmup):
     for _ in range(warmup):
-        t.step(U, w.dt)
+        t.step(U, dt)
     torch.cuda.synchronize()
     t.timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
-        t.step(U, w.dt)
+        t.step(U, dt)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
     kernel_ms, launches = t.timing(False)
+    return e0.elapsed_time(e1), kernel_ms, launches
+
+
+def leg_forward(pkg, torch, np, w, form, steps, warmup):
+    t = make_tracker(pkg, w, form)
+    inject_host(t, w)
+    U = field_of(torch, np, w, form)
+    ms, kernel_ms, launches = time_steps(torch, t, U, w.dt, steps, warmup)
     st = t.stats()
     t.close()
     del U
@@ -73,14 +100,68 @@ def time_form(pkg, torch, np, w, form, steps, warmup):
     return {"ms": ms, "kernel_ms": kernel_ms, "launches": launches, "stats": st}
 
 
+def leg_adjoint(pkg, torch, np, synth):
+    """Forward with checkpoints every 20 steps plus the adjoint, 64^3, 1e6."""
+    w = synth.get("adj64")
+    t = make_tracker(pkg, w, "fp32_local")
+    inject_host(t, w)
+    U = field_of(torch, np, w, "fp32_local")
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(w.nsteps):
+        t.step(U, w.dt, tape=20)
+    S = t.sources()
+    e1.record()
+    lam = (2.0 * S).contiguous()  # dL/dS of L = |S|^2, a stand-in for the misfit
+    dU, dd = t.backward(lam)
+    e2.record()
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    t.close()
+    return {"workload": w.name, "particles": w.P, "steps": w.nsteps, "checkpoint_every": 20,
+            "value": w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3), "unit": "particle-steps/s",
+            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all())}
+
+
+def leg_scale(pkg, torch, np, synth):
+    """512^3, 1.4e9 particles (60 % in one plume), field rotated 1 degree per
+    step on the second stream: throughput, overlap and the step kernel's
+    roofline at full size."""
+    w = synth.get("plume512")
+    t0 = time.perf_counter()
+    t = make_tracker(pkg, w, "fp32_local")
+    inject_device(t, w)
+    U0 = field_of(torch, np, w, "fp32_local")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    cs = w.rotation()
+    t.run_coupled(U0, w.rotation(2), w.dt)  # warm-up: two steps
+    t.timing(True)
+    field_ms, step_ms, total_ms = t.run_coupled(U0, cs, w.dt)
+    kernel_ms, launches = t.timing(False)
+    st = t.stats()
+    t.close()
+    del U0
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "particles": w.P, "steps": w.nsteps, "form": "fp32_local",
+            "value": w.P * w.nsteps / (total_ms / 1e3), "unit": "particle-steps/s",
+            "ms_per_step": total_ms / w.nsteps, "field_update_ms_per_step": field_ms / w.nsteps,
+            "particle_step_ms_per_step": step_ms / w.nsteps,
+            "overlap": "total vs field + particle stream time: "
+                       f"{total_ms:.2f} ms vs {field_ms + step_ms:.2f} ms",
+            "roofline": roofline("fp32_local", w, kernel_ms, launches, st["items"]),
+            "last_step_movers": st["movers"], "setup_s": setup_s}
+
+
 def cpu_baseline(w, np, steps=4, max_particles=4_000_000):
     from oracle.oracle import MeshParams, load
     orc = load()
     k = min(w.P, max_particles)
     x, up, d = w.particles(k)
-    U = w.field()
-    if True:  # the oracle gets the field the FP32 forms use, promoted
-        U = U.astype(np.float32).astype(np.float64)
+    # the oracle gets the field the binary32 forms use, promoted
+    U = w.field().astype(np.float32).astype(np.float64)
     mesh = MeshParams(**w.mesh_kwargs())
     t0 = time.perf_counter()
     orc.run(mesh, U, x, up, d, w.dt, steps)
@@ -97,6 +178,8 @@ def main():
     ap.add_argument("--workload", default="tg128")
     ap.add_argument("--form", default="fp32_local")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 1.4e9-particle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,12 +195,8 @@ def main():
 
     w = synth.get(args.workload)
     steps = args.steps if args.steps is not None else w.nsteps
-    res = time_form(pkg, torch, np, w, args.form, steps, args.warmup)
+    res = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup)
     value = w.P * steps / (res["ms"] / 1e3)
-    items = res["stats"]["items"]
-    bytes_launch, per_p, per_item = algorithmic_bytes(args.form, w.P, items, w.chunk_edge)
-    avg_kernel_s = res["kernel_ms"] / max(res["launches"], 1) / 1e3
-    achieved = bytes_launch / avg_kernel_s / 1e9
     out = {
         "metric": "particle-steps/s on 1 MI355X (fwd), FP32 chunk-local form",
         "value": value,
@@ -135,21 +214,22 @@ def main():
                    "form": args.form, "chunk_edge": w.chunk_edge,
                    "source_accumulation": "f32" if args.form == "fp32" else "f64",
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step", "avg_kernel_ms": avg_kernel_s * 1e3,
-                     "bytes_per_launch": bytes_launch,
-                     "model": f"{per_p} B/particle + {per_item} B/work item, {items} items"},
+        "roofline": roofline(args.form, w, res["kernel_ms"], res["launches"],
+                             res["stats"]["items"]),
         "step_kernel_share": res["kernel_ms"] / res["ms"],
         "last_step_movers": res["stats"]["movers"],
         "repacks": res["stats"]["repacks"],
     }
     if not args.no_fp64 and args.form != "fp64":
-        r64 = time_form(pkg, torch, np, w, "fp64", steps, args.warmup)
+        r64 = leg_forward(pkg, torch, np, w, "fp64", steps, args.warmup)
         out["fp64_form"] = {"value": w.P * steps / (r64["ms"] / 1e3),
                             "ms_per_step": r64["ms"] / steps,
                             "avg_kernel_ms": r64["kernel_ms"] / max(r64["launches"], 1)}
         out["speedup_vs_fp64_form"] = value / out["fp64_form"]["value"]
+    if not args.no_adjoint:
+        out["fwd_adjoint"] = leg_adjoint(pkg, torch, np, synth)
+    if not args.no_scale:
+        out["scale_512"] = leg_scale(pkg, torch, np, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, np)
     print(json.dumps(out), flush=True)

@@ -146,6 +146,39 @@ class Workload:
             return z, z.copy(), np.zeros(0)
         return np.concatenate(xs), np.concatenate(us), np.concatenate(ds)
 
+    def device_batch(self, b, batch=1 << 25, device="cuda"):
+        """Particles [b*batch, min(P, (b+1)*batch)) drawn on the GPU with torch's
+        seeded generator (same recipe, different random stream from batch()):
+        (x [k,3], up [k,3], d [k]) float64 device tensors.  For workloads too
+        large to draw on the host; a sample copied back is a valid oracle input."""
+        import torch
+        start = b * batch
+        k = min(self.P, start + batch) - start
+        f64 = torch.float64
+        if k <= 0:
+            z = torch.zeros((0, 3), dtype=f64, device=device)
+            return z, z.clone(), torch.zeros(0, dtype=f64, device=device)
+        seed = int(np.random.SeedSequence([self.seed, b, 77]).generate_state(1, np.uint64)[0])
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        L = torch.tensor(self.L, dtype=f64, device=device)
+        x = torch.rand((k, 3), generator=g, dtype=f64, device=device) * L
+        if self.plumes > 0:
+            centres = torch.from_numpy(self.plume_centres()).to(device)
+            in_plume = torch.rand(k, generator=g, dtype=f64, device=device) < self.plume_fraction
+            which = torch.randint(0, self.plumes, (k,), generator=g, device=device)
+            off = torch.randn((k, 3), generator=g, dtype=f64, device=device) * (self.plume_sigma * L)
+            xp = torch.remainder(centres[which] + off, L)
+            x = torch.where(in_plume[:, None], xp, x)
+            x = torch.where(x >= L, torch.zeros_like(x), x)
+        d = torch.exp(torch.randn(k, generator=g, dtype=f64, device=device) * self.d_sigma_ln
+                      + math.log(self.d_median))
+        up = torch.zeros((k, 3), dtype=f64, device=device)
+        return x.contiguous(), up, d
+
+    def n_device_batches(self, batch=1 << 25):
+        return (self.P + batch - 1) // batch
+
     def rotation(self, nsteps=None, first=0):
         """(cos theta_n, sin theta_n) for n = first .. first+nsteps-1, flattened."""
         nsteps = self.nsteps if nsteps is None else nsteps
