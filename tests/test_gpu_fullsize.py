@@ -1,0 +1,62 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+tg128: 128^3 mesh, 1e7 droplets, FP32 chunk-local form, the same tracker
+configuration bench.py times.  After warm-up steps the oracle advances a
+random sample of 20 000 particles, one by one, from the GPU's state with the
+field the GPU used, and the sample is compared with the GPU's next state;
+the deposited source is checked over all particles through the momentum
+balance (sum of sources = minus the particles' drag impulse).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import BAND, face_distance, fields, min_image, oracle_mesh, tracker, workload
+from oracle.oracle import load as load_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(s, idx):
+    return {k: v[idx].cpu().numpy() for k, v in s.items()}
+
+
+def test_tg128_sampled_parity():
+    import torch
+    w = workload("tg128")
+    t = tracker(w, "fp32_local")
+    for b in range(w.n_batches()):
+        t.inject(*w.batch(b))
+    Udev, Uor = fields(w, "fp32_local")
+    for _ in range(5):
+        t.step(Udev, w.dt)
+    rng = np.random.default_rng(128)
+    idx = torch.from_numpy(rng.choice(w.P, 20000, replace=False)).cuda()
+    orc = load_oracle()
+    mesh = oracle_mesh(w)
+    L = np.array(w.L)
+    for step in range(3):
+        s0 = t.particles()
+        a = _sample(s0, idx)
+        t.sources(reset=True)
+        t.step(Udev, w.dt)
+        s1 = t.particles()
+        b = _sample(s1, idx)
+        xo, uo, _ = orc.run(mesh, Uor, a["x"], a["up"], a["d"], w.dt, 1)
+        pos = np.abs(min_image(b["x"] - xo, L)).max() / L.max()
+        vel = np.abs(b["up"] - uo).max()
+        near = (face_distance(xo, w.h) < BAND).any(axis=1)
+        co = orc.cells(mesh, xo)
+        assert np.array_equal(co[~near], b["cell"][~near])
+        assert pos < 1e-5 and vel < 1e-5, (pos, vel)
+        # all particles: sum of the step's sources = minus the drag impulse
+        S = t.sources(reset=True)
+        m = (w.parcel_weight * w.rho_p * np.pi / 6.0) * s0["d"] ** 3
+        g = torch.tensor(w.g, dtype=torch.float64, device="cuda")
+        J = (m[:, None] * (s1["up"] - s0["up"] - g * w.dt)).sum(dim=0)
+        scale = (m[:, None] * (s1["up"] - s0["up"])).abs().sum(dim=0)
+        Ssum = S.reshape(3, -1).sum(dim=1) * float(np.prod(w.h))
+        resid = ((Ssum + J).abs() / scale).cpu().numpy()
+        print("step", step, "pos", pos, "vel", vel, "band", int(near.sum()), "balance", resid)
+        assert np.all(resid < 1e-6)
+    assert np.array_equal(s1["id"].cpu().numpy(), np.arange(w.P))
+    t.close()
