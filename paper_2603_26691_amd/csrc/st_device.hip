@@ -706,8 +706,55 @@ struct RebinArgs {
     int32_t epoch;
 };
 
+constexpr int kBigFill = 4096;  // chunks with more movers than this get a workgroup
+
+// One workgroup fills one chunk with many movers (same steps as the
+// per-wave fill below, with workgroup-wide scans).
+template <class T>
+__device__ void fill_big_chunk(const RebinArgs<T> &a, int64_t c, int32_t out, int32_t in)
+{
+    const View<T> &V = a.V;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int64_t base = V.base[c];
+    const int32_t cnt = V.cnt[c];
+    const int32_t ncnt = cnt - out + in;
+    int32_t *H = a.hole + base;
+    const int32_t *box = a.inbox + base;
+    if (ncnt >= cnt) {
+        for (int32_t r = tid; r < in; r += nt)
+            place_mover(V, base + (r < out ? H[r] : cnt + (r - out)), a.mv, box[r]);
+    } else {
+        int32_t k = 0;
+        for (int32_t j0 = 0; j0 < out; j0 += nt) {
+            const int32_t j = j0 + tid;
+            const int32_t h = j < out ? H[j] : 0;
+            const int32_t keep = (j < out && h < ncnt) ? 1 : 0;
+            int32_t tot;
+            const int32_t ex = block_excl_scan<int32_t>(keep, tot);
+            if (keep) H[k + ex] = h;   // below every entry a later round reads
+            k += tot;
+        }
+        __syncthreads();
+        for (int32_t r = tid; r < in; r += nt) place_mover(V, base + H[r], a.mv, box[r]);
+        int32_t placed = 0;
+        const int32_t tail = cnt - ncnt;
+        for (int32_t t0 = 0; t0 < tail; t0 += nt) {
+            const int32_t t = t0 + tid;
+            const int64_t slot = base + ncnt + t;
+            const int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
+            int32_t tot;
+            const int32_t ex = block_excl_scan<int32_t>(live, tot);
+            if (live) copy_slot(V, base + H[in + placed + ex], slot);
+            placed += tot;
+        }
+    }
+    if (tid == 0) V.cnt[c] = ncnt;
+    __syncthreads();
+}
+
 // One wave per chunk: the arrivals, and when the chunk shrank its live tail
-// particles, fill the vacated slots below the new count.
+// particles, fill the vacated slots below the new count.  Chunks with more
+// than kBigFill movers are left to a whole workgroup afterwards.
 template <class T>
 __device__ void fill_chunks(const RebinArgs<T> &a)
 {
@@ -718,6 +765,7 @@ __device__ void fill_chunks(const RebinArgs<T> &a)
          c += (int64_t)gridDim.x * wpb) {
         const int32_t out = a.out_cnt[c], in = a.in_cnt[c];
         if (out == 0 && in == 0) continue;
+        if (out + in > kBigFill) continue;
         const int64_t base = V.base[c];
         const int32_t cnt = V.cnt[c];
         const int32_t ncnt = cnt - out + in;
@@ -756,6 +804,10 @@ __device__ void fill_chunks(const RebinArgs<T> &a)
             }
         }
         if (lane == 0) V.cnt[c] = ncnt;
+    }
+    for (int64_t c = blockIdx.x; c < a.C; c += gridDim.x) {
+        const int32_t out = a.out_cnt[c], in = a.in_cnt[c];
+        if (out + in > kBigFill) fill_big_chunk(a, c, out, in);
     }
 }
 

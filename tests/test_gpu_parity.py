@@ -71,6 +71,14 @@ def test_lockstep_chunk_split_over_items(orc, form):
     _run_lockstep(orc, w, form, nsteps=3)
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_many_movers(orc, form):
+    # 16^3 mesh = 8 chunks of ~19000 droplets and a step of about 0.8 cells:
+    # thousands of chunk crossers per chunk and step (the workgroup-wide fill)
+    w = workload("tg32", n=(16, 16, 16), P=150000, noise=0.1)
+    _run_lockstep(orc, w, form, nsteps=3, dt=5e-3)
+
+
 @pytest.mark.parametrize("edge", [2, 4])
 def test_lockstep_small_chunks(orc, edge):
     w = workload("tg32", n=(8, 8, 16), L=(0.05, 0.05, 0.1), P=5000, noise=0.2, chunk_edge=edge)
