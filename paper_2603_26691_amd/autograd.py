@@ -40,7 +40,10 @@ class DepositFn(torch.autograd.Function):
         t = run.tracker
         if t.count() != 0:
             raise ValueError("DepositFn needs a tracker without particles")
-        t.inject(run.x0, run.up0, d.detach().to(torch.float64))
+        dev = t.device
+        x0 = torch.as_tensor(run.x0, dtype=torch.float64).to(dev)
+        up0 = torch.as_tensor(run.up0, dtype=torch.float64).to(dev)
+        t.inject(x0, up0, d.detach().to(dev, torch.float64))
         uf = u.detach().to(t.field_dtype).contiguous()
         t.sources(reset=True)
         for _ in range(run.nsteps):
