@@ -90,7 +90,10 @@ def time_steps(torch, t, U, dt, steps, warmup):
 
 def leg_forward(pkg, torch, np, w, form, steps, warmup):
     t = make_tracker(pkg, w, form)
-    inject_host(t, w)
+    if w.P > 50_000_000:
+        inject_device(t, w)   # too many to draw on the host in time
+    else:
+        inject_host(t, w)
     U = field_of(torch, np, w, form)
     ms, kernel_ms, launches = time_steps(torch, t, U, w.dt, steps, warmup)
     st = t.stats()
