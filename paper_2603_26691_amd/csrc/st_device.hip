@@ -357,7 +357,14 @@ struct StepArgs {
     T dt_h[3];               // dt / h per axis
     T tau_coef;
     T g[3];
+    T g_dt[3];               // g dt
+    T mass_coef;             // w rho_p pi / 6
+    T inv_V;                 // 1 / cell volume
 };
+
+// reciprocal: the hardware's (1 ulp) in binary32, a division in binary64
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD walks a contiguous range of work items (neighbouring chunks share
@@ -431,6 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     __shared__ A acc[3 * E3];
     __shared__ int32_t mslot[kMoverStage];
     __shared__ int32_t mcount, mbase_sh, hbase_sh;
+    __shared__ int32_t dcount[27], dbase[27];
 
     const int64_t item = xcd_remap(blockIdx.x, a.grid);
     if (item >= *a.nitems) return;
@@ -484,8 +492,6 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     __syncthreads();
 
     const T dt = a.dt;
-    const A inv_V = (A)p.inv_V;
-    const A dtA = (A)dt;
     const T fe = T(E), inv_e = T(1) / T(E);
     // groups of G consecutive slots; s0 is a multiple of G (chunk bases and
     // kSeg are), and a group that runs past s1 stays inside the chunk's room
@@ -547,7 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             // written as the velocity change, which keeps its relative
             // accuracy in binary32:  u_p' - u_p = dt (u_f - u_p + tau g) / (tau + dt)
             const T tau = a.tau_coef * dp * dp;
-            const T rD = dt / (tau + dt);
+            const T rD = dt * recip(tau + dt);
             T upn[3], xn[3];
             for (int ax = 0; ax < 3; ++ax) {
                 upn[ax] = up[ax] + rD * ((uf[ax] - up[ax]) + tau * a.g[ax]);
@@ -555,17 +561,15 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             }
 
             // drag impulse J = m (u_p' - u_p - g dt) = m dt (u_f - u_p - g dt) / (tau + dt),
-            // in the accumulator precision from the stored inputs; the fluid
+            // evaluated from the stored inputs (not from the rounded new
+            // velocity) and summed in the accumulator precision; the fluid
             // receives -J / V in the start-of-step cell
             if (a.deposit && valid) {
-                const A dA = (A)dp;
-                const A mass = (A)p.mass_coef * dA * dA * dA;
-                const A tauA = (A)p.tau_coef * dA * dA;
-                const A coef = -mass * dtA / (tauA + dtA) * inv_V;
+                const T coef = -(a.mass_coef * dp * dp * dp) * rD * a.inv_V;
                 const int cell = (cl[2] * E + cl[1]) * E + cl[0];
                 for (int ax = 0; ax < 3; ++ax) {
-                    const A slip = (A)uf[ax] - (A)up[ax] - (A)p.g[ax] * dtA;
-                    atomicAdd(&acc[ax * E3 + cell], coef * slip);
+                    const T slip = (uf[ax] - up[ax]) - a.g_dt[ax];
+                    atomicAdd(&acc[ax * E3 + cell], (A)(coef * slip));
                 }
             }
 
@@ -631,16 +635,80 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
         }
     }
 
-    // emit the staged movers with one reservation per workgroup
+    // Emit the staged movers: one reservation per workgroup in the mover
+    // list and the vacated-slot list, and one arrival-count reservation per
+    // neighbouring destination chunk (the 26 directions) instead of one per
+    // mover, which would serialise on the counters of crowded chunks.
     const int nm = min(mcount, kMoverStage);
     if (nm > 0) {
+        constexpr int NM = kMoverStage / kBlock;  // staged movers per thread
+        if (threadIdx.x < 27) dcount[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
             mbase_sh = atomicAdd(a.nmov, nm);
             hbase_sh = atomicAdd(&a.out_cnt[c], nm);
         }
         __syncthreads();
-        for (int j = threadIdx.x; j < nm; j += kBlock)
-            emit_mover(a, c, base, base + mslot[j], (int64_t)mbase_sh + j, (int64_t)hbase_sh + j);
+        T mx[NM], my[NM], mz[NM];
+        int32_t mdir[NM], mrank[NM];
+        int64_t mdest[NM];
+#pragma unroll
+        for (int u = 0; u < NM; ++u) {
+            const int j = threadIdx.x + u * kBlock;
+            mdir[u] = -1;
+            if (j < nm) {
+                const int64_t q = base + mslot[j];
+                mx[u] = V.ox[q];
+                my[u] = V.oy[q];
+                mz[u] = V.oz[q];
+                const int kx = rebase(mx[u], fe, inv_e);
+                const int ky = rebase(my[u], fe, inv_e);
+                const int kz = rebase(mz[u], fe, inv_e);
+                mdest[u] = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
+                                       wrapi(cz + kz, p.nc[2]));
+                if (abs(kx) <= 1 && abs(ky) <= 1 && abs(kz) <= 1) {
+                    mdir[u] = (kx + 1) + 3 * (ky + 1) + 9 * (kz + 1);
+                    mrank[u] = atomicAdd(&dcount[mdir[u]], 1);
+                } else {  // farther than one chunk: its own reservation
+                    mrank[u] = atomicAdd(&a.in_cnt[mdest[u]], 1);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 27 && dcount[threadIdx.x] > 0) {
+            const int dir = threadIdx.x;
+            const int64_t dc = chunk_index(p, wrapi(cx + dir % 3 - 1, p.nc[0]),
+                                           wrapi(cy + (dir / 3) % 3 - 1, p.nc[1]),
+                                           wrapi(cz + dir / 9 - 1, p.nc[2]));
+            dbase[dir] = atomicAdd(&a.in_cnt[dc], dcount[dir]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NM; ++u) {
+            const int j = threadIdx.x + u * kBlock;
+            if (j >= nm) continue;
+            const int64_t q = base + mslot[j];
+            const int64_t m = (int64_t)mbase_sh + j;
+            const int32_t id = V.id[q];
+            V.id[q] = -1 - id;
+            a.hole[base + hbase_sh + j] = mslot[j];
+            if (m < a.mcap) {
+                a.mv.ox[m] = mx[u];
+                a.mv.oy[m] = my[u];
+                a.mv.oz[m] = mz[u];
+                a.mv.vx[m] = V.vx[q];
+                a.mv.vy[m] = V.vy[q];
+                a.mv.vz[m] = V.vz[q];
+                a.mv.d[m] = V.d[q];
+                a.mv.id[m] = id;
+                a.mv.dest[m] = (int32_t)mdest[u];
+                const int32_t r = mdir[u] >= 0 ? dbase[mdir[u]] + mrank[u] : mrank[u];
+                // a rank beyond the room means the chunk overflows (the room
+                // check sees it too); the entry is then never read
+                if (r < V.room[mdest[u]]) a.inbox[V.base[mdest[u]] + r] = (int32_t)m;
+            } else {
+                a.flags[F_OVERFLOW] = a.epoch;
+            }
+        }
     }
 }
 
@@ -706,7 +774,8 @@ struct RebinArgs {
     int32_t epoch;
 };
 
-constexpr int kBigFill = 4096;  // chunks with more movers than this get a workgroup
+constexpr int kFillBlock = 1024;  // threads per workgroup of the fill
+constexpr int kBigFill = 256;     // chunks with more movers than this get a workgroup
 
 // One workgroup fills one chunk with many movers (same steps as the
 // per-wave fill below, with workgroup-wide scans).
@@ -840,7 +909,7 @@ __device__ void rekey_count(const RebinArgs<T> &a)
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_fill_or_count(RebinArgs<T> a)
+__global__ void __launch_bounds__(kFillBlock) k_fill_or_count(RebinArgs<T> a)
 {
     if (full_rebin(a.flags, a.epoch)) rekey_count(a);
     else fill_chunks(a);
@@ -1206,11 +1275,11 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
 {
     const RebinArgs<T> a = rebin_args<T>(c, npend);
     const int64_t C = c->C;
-    int64_t g = (C + 3) / 4;                      // one wave per chunk in the fill
+    int64_t g = (C + kFillBlock / 64 - 1) / (kFillBlock / 64);  // a wave per chunk
     const int64_t gi = c->max_items;              // one block per item in the count
     if (gi > g) g = gi;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(kFillBlock), 0, s, a);
     const int64_t total = c->count + npend;
     Rooms rooms{c->new_cnt, c->slots - total - (int64_t)kAlign * C,
                 total + (int64_t)kSlackMin * C, c->nroom};
@@ -1286,6 +1355,9 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
             a.g[ax] = (T)c->prm.g[ax];
         }
         a.tau_coef = (T)c->prm.tau_coef;
+        for (int ax = 0; ax < 3; ++ax) a.g_dt[ax] = (T)(c->prm.g[ax] * dt);
+        a.mass_coef = (T)c->prm.mass_coef;
+        a.inv_V = (T)c->prm.inv_V;
         hipEvent_t ev[2] = {nullptr, nullptr};
         if (c->timing) {
             for (int k = 0; k < 2; ++k) {
