@@ -62,13 +62,36 @@ def field_of(torch, np, w, form):
     return torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
 
 
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2603_26691_amd", "csrc", "st_device.hip")
+
+
+def measured_traffic(workload, form):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
+    plain 1 GiB device copy), or None when there is no record for this
+    workload or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{form}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
 def roofline(form, w, kernel_ms, launches, items):
     bytes_launch, per_p, per_item = algorithmic_bytes(form, w.P, items, w.chunk_edge)
     avg_s = kernel_ms / max(launches, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_step",
-            "avg_kernel_ms": avg_s * 1e3, "bytes_per_launch": bytes_launch,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, form),
+            "kernel": "k_step", "avg_kernel_ms": avg_s * 1e3, "bytes_per_launch": bytes_launch,
             "model": f"{per_p} B/particle + {per_item} B/work item, {items} items"}
 
 
