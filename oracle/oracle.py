@@ -98,6 +98,7 @@ class Oracle:
             "or_run": (None, [M, _P, _I64, _P, _P, _P, _D, _I32, _I32, _P]),
             "or_run_rotating": (None, [M, _P, _P, _I64, _P, _P, _P, _D, _I32, _P]),
             "or_adjoint": (ctypes.c_int, [M, _P, _I64, _P, _P, _P, _D, _I32, _P, _P, _P]),
+            "or_ec_estimate": (None, [_I64, _I32, _P, _P, _P, _P]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(lib, name)
@@ -167,6 +168,19 @@ class Oracle:
         self.lib.or_run_rotating(ctypes.byref(m), _ptr(U0), _ptr(cs), x.shape[0], _ptr(x),
                                  _ptr(up), _ptr(d), float(dt), int(nsteps), _ptr(S))
         return x, up, S
+
+    def ec_estimate(self, kind, S_last, state):
+        """One extrapolator-corrector call; `state` is a dict with arrays
+        'S_prev2' and 'ext_prev' (updated in place).  Returns the source to
+        apply."""
+        S_last = _f64(S_last)
+        for k in ("S_prev2", "ext_prev"):
+            assert state[k].dtype == np.float64 and state[k].flags.c_contiguous
+            assert state[k].size == S_last.size
+        out = np.empty_like(S_last)
+        self.lib.or_ec_estimate(S_last.size, int(kind), _ptr(S_last), _ptr(state["S_prev2"]),
+                                _ptr(state["ext_prev"]), _ptr(out))
+        return out
 
     def adjoint(self, mesh, Uf, x0, up0, d, dt, nsteps, lam):
         """Returns (dL/dUf, dL/dd) for dL/dSu_int = lam."""

@@ -231,6 +231,20 @@ void or_run_rotating(const or_mesh *m, const double *U0, const double *cs,
     free(Un);
 }
 
+void or_ec_estimate(int64_t n, int32_t kind, const double *S_last, double *S_prev2,
+                    double *ext_prev, double *applied)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double correction = S_last[i] - ext_prev[i];
+        double extrapolation = 0.0;
+        if (kind == 1) extrapolation = S_last[i];
+        if (kind == 2) extrapolation = 2.0 * S_last[i] - S_prev2[i];
+        applied[i] = correction + extrapolation;
+        ext_prev[i] = extrapolation;
+        S_prev2[i] = S_last[i];
+    }
+}
+
 int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
                const double *x0, const double *up0, const double *d,
                double dt, int32_t nsteps, const double *lambda, double *Ubar,

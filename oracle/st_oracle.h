@@ -94,6 +94,19 @@ void or_run_rotating(const or_mesh *m, const double *U0, const double *cs,
                      int64_t np, double *x, double *up, const double *d,
                      double dt, int32_t nsteps, double *Su_int);
 
+/* Extrapolator-corrector for sources that arrive one step late (paper
+ * Sec. 2.4).  At the current step only the actual source of the previous
+ * step, S_last, is available.  The corrector is S_last minus the
+ * extrapolation that stood in for it one step earlier (ext_prev); the
+ * extrapolation for the current step is 0 (kind 0, zero), S_last (kind 1,
+ * constant) or 2 S_last - S_prev2 (kind 2, linear), S_prev2 being the actual
+ * source one step further back.  The source to apply is corrector plus
+ * extrapolation; then ext_prev <- extrapolation, S_prev2 <- S_last.  All
+ * arrays hold n values (cells times components); ext_prev and S_prev2 start
+ * at zero. */
+void or_ec_estimate(int64_t n, int32_t kind, const double *S_last, double *S_prev2,
+                    double *ext_prev, double *applied);
+
 /* Reverse-mode derivative of nsteps single-sub-step calls of or_step
  * starting from (x0, up0), for a loss whose derivative with respect to the
  * time-integrated source Su_int is lambda ([3][n2][n1][n0]).  Adds dL/dUf to

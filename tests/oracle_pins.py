@@ -390,11 +390,95 @@ def pin_adjoint_fd(orc):
     assert checked >= 20, "too few field FD samples"
 
 
+# ---------------------------------------------------------------------------
+# extrapolator-corrector (paper Sec. 2.4) and two-way coupling (Sec. 3.1)
+# ---------------------------------------------------------------------------
+def pin_ec_conservative(orc):
+    # the paper: subtracting the previous estimate makes the procedure
+    # conservative over time -- the applied sources add up to the actual ones
+    # plus the extrapolation still outstanding
+    rng = np.random.default_rng(31)
+    s = rng.normal(size=(14, 40))
+    for kind in (0, 1, 2):
+        st = {"S_prev2": np.zeros(40), "ext_prev": np.zeros(40)}
+        cum = np.zeros(40)
+        for k in range(14):
+            cum += orc.ec_estimate(kind, s[k], st)
+            prev = s[k - 1] if k > 0 else np.zeros(40)
+            outstanding = [np.zeros(40), s[k], 2 * s[k] - prev][kind]
+            assert np.allclose(cum, s[:k + 1].sum(axis=0) + outstanding, rtol=0, atol=1e-12), \
+                f"conservation over time, extrapolator {kind}, call {k}"
+
+
+def pin_ec_exact_histories(orc):
+    # a constant source is applied unchanged once the history is filled; a
+    # linear history is predicted exactly by the constant (with its
+    # corrector) and the linear extrapolator; the zero extrapolator applies
+    # each source one step late
+    a, b = 0.7, -0.3
+    lin = [a + b * k for k in range(12)]
+    for kind in (0, 1, 2):
+        st = {"S_prev2": np.zeros(1), "ext_prev": np.zeros(1)}
+        stc = {"S_prev2": np.zeros(1), "ext_prev": np.zeros(1)}
+        for k in range(11):
+            got = orc.ec_estimate(kind, np.array([lin[k]]), st)[0]
+            gotc = orc.ec_estimate(kind, np.array([2.5]), stc)[0]
+            if k >= 2:
+                assert abs(gotc - 2.5) < 1e-14, f"constant source, extrapolator {kind}"
+            if kind == 0:
+                assert abs(got - lin[k]) < 1e-14, "zero extrapolator lags one step"
+            elif k >= kind:
+                assert abs(got - lin[k + 1]) < 1e-14, f"linear history, extrapolator {kind}"
+
+
+def _two_way_0d(orc, dt, t_end, m_ratio=1.0):
+    # one droplet at 1 m/s in quiescent fluid on a one-chunk periodic mesh;
+    # the fluid is uniform (0-D) and takes the deposited momentum
+    L = 1e-3
+    d = 100e-6
+    m_p = 1000.0 * math.pi * d ** 3 / 6.0
+    m_f = m_p / m_ratio
+    mesh = MeshParams(n=(2, 2, 2), L=(L, L, L), g=(0.0, 0.0, 0.0), rho_f=m_f / L ** 3,
+                      rho_p=1000.0, mu_f=MU_F)
+    x = np.array([[0.3 * L, 0.4 * L, 0.5 * L]])
+    up = np.array([[1.0, 0.0, 0.0]])
+    uf = np.zeros(3)
+    V = (L / 2) ** 3
+    for _ in range(int(round(t_end / dt))):
+        U = np.empty(mesh.field_shape)
+        for c in range(3):
+            U[c] = uf[c]
+        x, up, S = orc.run(mesh, U, x, up, np.array([d]), dt, 1)
+        uf = uf + S.reshape(3, -1).sum(axis=1) * V / m_f   # conventional coupling
+    return up[0], uf, m_p, m_f
+
+
+def pin_two_way_relaxation(orc):
+    # relative velocity decays at (1 + m_p/m_f)/tau and the total momentum is
+    # conserved: the coupled scheme converges to that solution as dt halves
+    # (at least first order; this linear two-body system shows second)
+    d = 100e-6
+    tau = _stokes_tau(d)
+    t_end = 2 * tau
+    errs = []
+    for k in (8, 16, 32, 64):
+        up, uf, m_p, m_f = _two_way_0d(orc, tau / k, t_end)
+        P = m_p * 1.0
+        assert abs(m_p * up[0] + m_f * uf[0] - P) < 1e-12 * P, "total momentum"
+        w = math.exp(-(1 + m_p / m_f) * t_end / tau)
+        uf_exact = (P - m_p * w) / (m_p + m_f)
+        errs.append(abs(uf[0] - uf_exact))
+    slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(0.9 < s < 2.2 for s in slopes), f"two-way relaxation slopes {slopes}"
+    assert errs[-1] < 1e-5, f"two-way relaxation error {errs[-1]}"
+
+
 ALL_PINS = [
     pin_cell_brute_force, pin_wrap, pin_interp_cell_centre, pin_interp_affine,
     pin_interp_shift, pin_interp_ngp, pin_interp_transpose, pin_closed_form_uniform,
     pin_terminal_velocity, pin_first_order, pin_conservation, pin_start_cell_deposit,
-    pin_rotating_field, pin_adjoint_fd,
+    pin_rotating_field, pin_adjoint_fd, pin_ec_conservative, pin_ec_exact_histories,
+    pin_two_way_relaxation,
 ]
 
 

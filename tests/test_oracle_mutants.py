@@ -85,6 +85,16 @@ MUTANTS = {
         ("mbar * 3.0 * mass / d[p]", "mbar * 2.0 * mass / d[p]"),
     "adjoint: dtau/dd factor":
         ("taubar * 2.0 * tau / d[p]", "taubar * tau / d[p]"),
+    "extrapolator-corrector: corrector sign":
+        ("double correction = S_last[i] - ext_prev[i];", "double correction = S_last[i] + ext_prev[i];"),
+    "extrapolator-corrector: linear coefficients swapped":
+        ("2.0 * S_last[i] - S_prev2[i]", "2.0 * S_prev2[i] - S_last[i]"),
+    "extrapolator-corrector: history not advanced":
+        ("S_prev2[i] = S_last[i];", ";"),
+    "extrapolator-corrector: extrapolation not remembered":
+        ("ext_prev[i] = extrapolation;", ";"),
+    "extrapolator-corrector: constant extrapolator uses the older source":
+        ("if (kind == 1) extrapolation = S_last[i];", "if (kind == 1) extrapolation = S_prev2[i];"),
 }
 
 
