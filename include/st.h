@@ -166,6 +166,32 @@ st_status st_run_coupled(st_ctx *ctx, const void *u0, const double *cs,
                          int32_t nsteps, double dt, float *field_ms,
                          float *step_ms, float *total_ms, void *hip_stream);
 
+/* Extrapolators of the extrapolator-corrector (paper Sec. 2.4). */
+typedef enum {
+    ST_EXTRAP_ZERO = 0,    /* no estimate: sources are applied one step late */
+    ST_EXTRAP_CONST = 1,   /* the last available source */
+    ST_EXTRAP_LINEAR = 2   /* linear extrapolation from the last two sources */
+} st_extrapolator;
+
+/* Extrapolator-corrector for a fluid solver that runs one step ahead of the
+ * particles (paper Sec. 2.4, the estimated source of the current step).  At
+ * the current step only S_last, the actual time-integrated source of the
+ * previous step (e.g. from st_get_sources with reset), is available.  Per
+ * cell and component the call returns in `applied`
+ *   (S_last - E_prev) + E_now,
+ * the corrector (what the previous step's extrapolation E_prev missed) plus
+ * the extrapolation E_now for the current step: 0, S_last, or
+ * 2 S_last - S_prev (S_prev: the S_last of the previous call), and keeps
+ * E_now and S_last for the next call.  Summed over calls, the applied
+ * sources equal the actual ones plus the extrapolation still outstanding
+ * (conservative over time).  S_last and applied are [3][n2][n1][n0]
+ * binary64; `kind` is an st_extrapolator. */
+st_status st_ec_estimate(st_ctx *ctx, int32_t kind, const double *S_last, double *applied,
+                         int on_device, void *hip_stream);
+
+/* Clears the extrapolator-corrector's history (E_prev = S_prev = 0). */
+st_status st_ec_reset(st_ctx *ctx, void *hip_stream);
+
 /* Counters of the last st_step (host memory): movers, full repacks so far,
  * particles, store slots, work items (chunk runs of the step kernel).  Any
  * pointer may be NULL.  Synchronises the stream. */

@@ -60,7 +60,10 @@ SIGNATURES = {
     "st_stats": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                       ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
     "st_timing": (_I, [_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
+    "st_ec_estimate": (_I, [_P, _I32, _P, _P, _I, _P]),
+    "st_ec_reset": (_I, [_P, _P]),
 }
+EXTRAPOLATORS = {"zero": 0, "const": 1, "linear": 2}
 
 _lib = None
 

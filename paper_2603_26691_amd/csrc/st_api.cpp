@@ -52,7 +52,7 @@ void free_all(st_ctx *c)
     void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->cursor,
                        c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
                        c->scan_tmp, c->flags, c->src, c->stage64, c->fieldbuf[0],
-                       c->fieldbuf[1]};
+                       c->fieldbuf[1], c->ec_prev, c->ec_ext};
     for (void *p : singles) (void)hipFree(p);
     for (auto &sn : c->snaps) (void)hipFree(sn.buf);
     c->snaps.clear();
@@ -505,6 +505,57 @@ st_status st_run_coupled(st_ctx *c, const void *u0, const double *cs, int32_t ns
     if (ev_start) (void)hipEventDestroy(ev_start);
     cleanup();
     if (e != hipSuccess) return dev_fail(c, e, "st_run_coupled");
+    return ST_OK;
+}
+
+st_status st_ec_reset(st_ctx *c, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    ST_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+    if (!c->ec_prev) {
+        if (hipMalloc((void **)&c->ec_prev, (size_t)n * 8) != hipSuccess)
+            return fail(c, ST_ERR_OOM, "st_ec_reset: history buffers");
+        if (hipMalloc((void **)&c->ec_ext, (size_t)n * 8) != hipSuccess) {
+            (void)hipFree(c->ec_prev);
+            c->ec_prev = nullptr;
+            return fail(c, ST_ERR_OOM, "st_ec_reset: history buffers");
+        }
+    }
+    ST_HIP(st::launch_zero_f64(c->ec_prev, n, s));
+    ST_HIP(st::launch_zero_f64(c->ec_ext, n, s));
+    return ST_OK;
+}
+
+st_status st_ec_estimate(st_ctx *c, int32_t kind, const double *S_last, double *applied,
+                         int on_device, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    if (!S_last || !applied) return fail(c, ST_ERR_INVALID, "st_ec_estimate: null array");
+    if (kind < ST_EXTRAP_ZERO || kind > ST_EXTRAP_LINEAR)
+        return fail(c, ST_ERR_INVALID, "st_ec_estimate: unknown extrapolator");
+    if (!c->ec_prev) {
+        st_status r = st_ec_reset(c, hip_stream);
+        if (r != ST_OK) return r;
+    }
+    ST_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const size_t n = 3 * (size_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+    if (on_device) {
+        ST_HIP(st::launch_ec(c, kind, S_last, applied, s));
+        return ST_OK;
+    }
+    double *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, 2 * n * 8) != hipSuccess)
+        return fail(c, ST_ERR_OOM, "st_ec_estimate: temporaries");
+    hipError_t e = hipMemcpyAsync(tmp, S_last, n * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = st::launch_ec(c, kind, tmp, tmp + n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(applied, tmp + n, n * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return dev_fail(c, e, "st_ec_estimate");
     return ST_OK;
 }
 

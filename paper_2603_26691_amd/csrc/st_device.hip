@@ -1459,6 +1459,45 @@ hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, 
     });
 }
 
+// extrapolator-corrector, elementwise over cells and components
+__global__ void k_ec(int64_t n, int kind, const double *S_last, double *S_prev, double *E_prev,
+                     double *applied)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double s = S_last[i];
+        const double corrector = s - E_prev[i];
+        double e = 0.0;
+        if (kind == 1) e = s;
+        if (kind == 2) e = 2.0 * s - S_prev[i];
+        applied[i] = corrector + e;
+        E_prev[i] = e;
+        S_prev[i] = s;
+    }
+}
+
+__global__ void k_zero_f64(double *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_ec(st_ctx *c, int kind, const double *S_last, double *applied, hipStream_t s)
+{
+    const int64_t n = 3 * (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
+    hipLaunchKernelGGL(k_ec, dim3(grid_for(n, 16384)), dim3(256), 0, s, n, kind, S_last,
+                       c->ec_prev, c->ec_ext, applied);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n, 16384)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 size_t snapshot_bytes(const st_ctx *c)
 {
     return snap_layout(c->slots, c->tsize, c->C, c->max_items).bytes;

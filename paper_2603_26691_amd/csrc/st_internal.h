@@ -148,6 +148,11 @@ struct st_ctx {
     void *fieldbuf[2] = {};
     hipStream_t side = nullptr;
 
+    // extrapolator-corrector history ([3][ncell] binary64 each), allocated
+    // on first use
+    double *ec_prev = nullptr;     // S_last of the previous call
+    double *ec_ext = nullptr;      // extrapolation made at the previous call
+
     // step-kernel timing (events recorded around each launch)
     int timing = 0;
     std::vector<hipEvent_t> tev;   // pairs: start, stop
@@ -172,6 +177,8 @@ hipError_t launch_get_sources(st_ctx *c, double *out, int reset, hipStream_t s);
 hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, double sn,
                                hipStream_t s);
 hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s);
+hipError_t launch_ec(st_ctx *c, int kind, const double *S_last, double *applied, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 size_t snapshot_bytes(const st_ctx *c);
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s);
 

@@ -159,6 +159,20 @@ class Tracker:
                                        nsteps, float(dt), *args, _stream()), self.ctx)
         return (f.value, s.value, t.value) if timed else None
 
+    def ec_estimate(self, kind, S_last):
+        """Source to apply at the current step from the previous step's actual
+        source (extrapolator-corrector, kind "zero", "const" or "linear")."""
+        k = N.EXTRAPOLATORS[kind] if isinstance(kind, str) else int(kind)
+        S_last = S_last.to(self.device, torch.float64).contiguous()
+        assert tuple(S_last.shape) == self.field_shape
+        out = torch.empty_like(S_last)
+        N.check(N.lib().st_ec_estimate(self.ctx, k, _dptr(S_last), _dptr(out), 1, _stream()),
+                self.ctx)
+        return out
+
+    def ec_reset(self):
+        N.check(N.lib().st_ec_reset(self.ctx, _stream()), self.ctx)
+
     def stats(self):
         m, r, p, s, i = (ctypes.c_int64() for _ in range(5))
         N.check(N.lib().st_stats(self.ctx, ctypes.byref(m), ctypes.byref(r), ctypes.byref(p),
