@@ -573,16 +573,15 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
                 }
             }
 
-            // relocate: stayers keep re-based offsets; movers keep un-rebased
-            // ones (relative to this chunk) until they are emitted
-            T xr[3] = {xn[0], xn[1], xn[2]};
-            const int kx = rebase(xr[0], fe, inv_e);
-            const int ky = rebase(xr[1], fe, inv_e);
-            const int kz = rebase(xr[2], fe, inv_e);
-            const bool mover = (kx | ky | kz) != 0;
-            X[k] = mover ? xn[0] : xr[0];
-            Y[k] = mover ? xn[1] : xr[1];
-            Z[k] = mover ? xn[2] : xr[2];
+            // relocate: a particle whose new offset left [0, E) on some axis
+            // crossed into another chunk; it keeps the un-rebased offsets
+            // (relative to this chunk) until it is emitted and re-based.  A
+            // particle that stays needs no re-basing.
+            const bool mover = xn[0] < T(0) || xn[0] >= fe || xn[1] < T(0) || xn[1] >= fe ||
+                               xn[2] < T(0) || xn[2] >= fe;
+            X[k] = xn[0];
+            Y[k] = xn[1];
+            Z[k] = xn[2];
             UX[k] = upn[0];
             UY[k] = upn[1];
             UZ[k] = upn[2];
