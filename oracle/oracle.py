@@ -20,6 +20,8 @@ class _Mesh(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32 * 3),
         ("interp", ctypes.c_int32),
+        ("drag", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("L", ctypes.c_double * 3),
         ("rho_f", ctypes.c_double),
         ("mu_f", ctypes.c_double),
@@ -40,11 +42,13 @@ class MeshParams:
     rho_p: float = 1000.0
     parcel_weight: float = 1.0
     interp: int = 0  # 0 trilinear, 1 nearest grid point
+    drag: int = 0    # 0 Stokes, 1 Schiller-Naumann
 
     def to_c(self):
         m = _Mesh()
         m.n[:] = [int(v) for v in self.n]
         m.interp = int(self.interp)
+        m.drag = int(self.drag)
         m.L[:] = [float(v) for v in self.L]
         m.rho_f = float(self.rho_f)
         m.mu_f = float(self.mu_f)
@@ -94,6 +98,7 @@ class Oracle:
             "or_interp_transpose": (None, [M, _P, _P, _P]),
             "or_tau": (_D, [M, _D]),
             "or_mass": (_D, [M, _D]),
+            "or_drag_factor": (_D, [M, _D, _P]),
             "or_step": (None, [M, _P, _I64, _P, _P, _P, _D, _I32, _P]),
             "or_run": (None, [M, _P, _I64, _P, _P, _P, _D, _I32, _I32, _P]),
             "or_run_rotating": (None, [M, _P, _P, _I64, _P, _P, _P, _D, _I32, _P]),
@@ -139,6 +144,11 @@ class Oracle:
     def mass(self, mesh, d):
         m = mesh.to_c()
         return self.lib.or_mass(ctypes.byref(m), float(d))
+
+    def drag_factor(self, mesh, d, slip):
+        m = mesh.to_c()
+        s = _f64(slip, (3,))
+        return self.lib.or_drag_factor(ctypes.byref(m), float(d), _ptr(s))
 
     # -- time stepping -----------------------------------------------------
     def run(self, mesh, Uf, x, up, d, dt, nsteps, nsub=1, Su_int=None):

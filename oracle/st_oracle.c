@@ -78,6 +78,18 @@ double or_mass(const or_mesh *m, double d)
     return m->parcel_weight * m->rho_p * OR_PI * d * d * d / 6.0;
 }
 
+static double slip_reynolds(const or_mesh *m, double d, const double slip[3])
+{
+    double s = sqrt(slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2]);
+    return m->rho_f * s * d / m->mu_f;
+}
+
+double or_drag_factor(const or_mesh *m, double d, const double slip[3])
+{
+    if (m->drag != 1) return 1.0;
+    return 1.0 + 0.15 * pow(slip_reynolds(m, d, slip), 0.687);
+}
+
 /*
  * Interpolation stencil at position x: 8 corner cells (x-index fastest in
  * the corner number), their weights and the weights' gradient with respect
@@ -176,7 +188,8 @@ static void particle_substep(const or_mesh *m, const double *Uf, double x[3],
     or_cell(m, x, c0);
     double ufp[3];
     or_interp(m, Uf, x, ufp);
-    double tau = or_tau(m, d);
+    double slip[3] = {ufp[0] - up[0], ufp[1] - up[1], ufp[2] - up[2]};
+    double tau = or_tau(m, d) / or_drag_factor(m, d, slip);
     double mass = or_mass(m, d);
     double V = cell_volume(m);
     double up_new[3], J[3];
@@ -271,9 +284,8 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
     double V = cell_volume(m);
     for (int64_t p = 0; p < np; ++p) {
         double xbar[3] = {0, 0, 0}, ubar[3] = {0, 0, 0}, db = 0.0;
-        double tau = or_tau(m, d[p]);
+        double tau_s = or_tau(m, d[p]);
         double mass = or_mass(m, d[p]);
-        double D = tau + dt;
         for (int32_t n = nsteps - 1; n >= 0; --n) {
             const double *x = xs + per * n + 3 * p;
             const double *up = us + per * n + 3 * p;
@@ -284,6 +296,10 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
             make_stencil(m, x, &st);
             double ufp[3], up_new[3];
             or_interp(m, Uf, x, ufp);
+            double slip[3] = {ufp[0] - up[0], ufp[1] - up[1], ufp[2] - up[2]};
+            double f = or_drag_factor(m, d[p], slip);
+            double tau = tau_s / f;
+            double D = tau + dt;
             for (int a = 0; a < 3; ++a)
                 up_new[a] = (tau * up[a] + dt * ufp[a] + tau * dt * m->g[a]) / D;
 
@@ -301,6 +317,25 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
                 taubar += wbar[a] * (up[a] + dt * m->g[a] - up_new[a]) / D;
                 ubar[a] = -mass * Jbar[a] + tau / D * wbar[a];
             }
+            /* tau = tau_s / f: the Stokes part and, for Schiller-Naumann, the
+             * drag factor f = 1 + 0.15 Re^0.687 with Re = rho_f |s| d / mu_f
+             * of the slip s = u_f - u_p (dRe/ds = Re s / |s|^2, dRe/dd = Re/d;
+             * at zero slip the derivative is taken as zero). */
+            double tausbar = taubar / f;
+            double Rebar = 0.0, Re = 0.0;
+            if (m->drag == 1) {
+                double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
+                Re = slip_reynolds(m, d[p], slip);
+                if (Re > 0.0) {
+                    double fbar = -taubar * tau / f;
+                    Rebar = fbar * 0.15 * 0.687 * pow(Re, 0.687 - 1.0);
+                    for (int a = 0; a < 3; ++a) {
+                        double sbar = Rebar * Re * slip[a] / s2;
+                        ufbar[a] += sbar;
+                        ubar[a] -= sbar;
+                    }
+                }
+            }
             /* Interpolation: u_f(x) = sum_k w_k(x) U[k]. */
             for (int k = 0; k < 8; ++k) {
                 double dot = 0.0;
@@ -315,7 +350,8 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
             }
             /* tau = rho_p d^2/(18 mu): dtau/dd = 2 tau/d;
              * m = w rho_p pi d^3/6:   dm/dd = 3 m/d. */
-            db += taubar * 2.0 * tau / d[p] + mbar * 3.0 * mass / d[p];
+            db += tausbar * 2.0 * tau_s / d[p] + mbar * 3.0 * mass / d[p];
+            if (Re > 0.0) db += Rebar * Re / d[p];
         }
         dbar[p] = db;
     }

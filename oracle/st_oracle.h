@@ -10,11 +10,13 @@
  * What is computed (paper, Sec. 2.1 "Governing equations" and Sec. 2.5
  * "Further implementation details"):
  *   - Newton's law for a particle, dx_p/dt = u_p and m_p du_p/dt = sum F
- *     (Sec. 2.1, particle equations of motion), with Stokes drag plus gravity
- *     as the forces (the paper keeps only drag; gravity and the Stokes limit
- *     come from the workload definition and are documented readings);
+ *     (Sec. 2.1, particle equations of motion), with drag plus gravity as
+ *     the forces (the paper keeps only drag; gravity comes from the workload
+ *     definition and is a documented reading).  The drag is Stokes drag or
+ *     the paper's Schiller-Naumann correction of it (Sec. 2.1);
  *   - semi-implicit Euler: drag implicit, gravity explicit, position advanced
- *     with the new velocity (Sec. 2.5);
+ *     with the new velocity (Sec. 2.5); with Schiller-Naumann the correction
+ *     factor is taken from the slip at the start of the step;
  *   - the momentum source S_u = (1/V_cell) d(m_p u_p)/dt of Sec. 2.1, read as
  *     the fluid receiving minus the drag impulse, deposited into the cell
  *     that contains the particle at the start of the step (Sec. 2.5);
@@ -41,8 +43,10 @@ extern "C" {
 typedef struct {
     int32_t n[3];          /* cells per axis */
     int32_t interp;        /* 0 = trilinear, 1 = nearest grid point */
+    int32_t drag;          /* 0 = Stokes, 1 = Schiller-Naumann (Sec. 2.1) */
+    int32_t reserved;
     double  L[3];          /* domain extent per axis [m] */
-    double  rho_f;         /* fluid density [kg/m^3] (not used by the drag law) */
+    double  rho_f;         /* fluid density [kg/m^3] (Reynolds number only) */
     double  mu_f;          /* fluid dynamic viscosity [Pa s] */
     double  g[3];          /* gravitational acceleration [m/s^2] */
     double  rho_p;         /* particle material density [kg/m^3] */
@@ -74,6 +78,12 @@ void or_interp_transpose(const or_mesh *m, const double x[3],
  * m_p = w rho_p pi d^3 / 6. */
 double or_tau(const or_mesh *m, double d);
 double or_mass(const or_mesh *m, double d);
+
+/* Drag factor f relative to Stokes drag for the slip u_f - u_p: 1 (Stokes) or
+ * 1 + 0.15 Re^0.687 with Re = rho_f |u_f - u_p| d / mu_f (Schiller-Naumann).
+ * A step uses the effective response time tau / f, f taken with the slip at
+ * the start of the step (drag coefficient explicit, velocity implicit). */
+double or_drag_factor(const or_mesh *m, double d, const double slip[3]);
 
 /* One call of the Lagrangian step on np particles: nsub sub-steps of dt/nsub
  * with the field held fixed.  x, up updated in place ([np][3]); the time

@@ -11,6 +11,10 @@ disagrees with something the paper or the mathematics fixes:
     first-order convergence to the analytic Stokes-drag solution
     (Sec. 2.5 states first order);
   * the textbook Stokes settling speed of a 20 um water droplet in air;
+  * Schiller-Naumann drag (Sec. 2.1): the settling speed from the force
+    balance with the drag coefficient C_D = 24/Re (1 + 0.15 Re^0.687), solved
+    by bisection, and the measured fall speeds of 0.2 and 0.4 mm raindrops;
+    the one-step acceleration against that drag force for a 3-D slip;
   * momentum conservation between particles and deposited sources
     (Sec. 2.1, momentum source), and the start-of-step containing-cell
     deposit;
@@ -260,12 +264,78 @@ def pin_first_order(orc):
 
 
 # ---------------------------------------------------------------------------
+# Schiller-Naumann drag (paper Sec. 2.1)
+# ---------------------------------------------------------------------------
+RHO_F = 1.2
+G = 9.81
+
+
+def _sn_drag_force(slip, d):
+    # Drag of a sphere from the drag coefficient: F = 1/2 rho_f |s| s A C_D,
+    # A = pi d^2 / 4, with the Schiller-Naumann correlation
+    # C_D = 24 / Re (1 + 0.15 Re^0.687), Re = rho_f |s| d / mu_f.
+    s = float(np.linalg.norm(slip))
+    Re = RHO_F * s * d / MU_F
+    cd = 24.0 / Re * (1.0 + 0.15 * Re ** 0.687)
+    return 0.5 * RHO_F * s * np.asarray(slip) * (math.pi * d * d / 4.0) * cd
+
+
+def _sn_settling_speed(d):
+    # bisection on the balance drag(v) = weight (no buoyancy, as in the model)
+    m = RHO_P * math.pi * d ** 3 / 6.0
+    lo, hi = 0.0, 100.0
+    for _ in range(200):
+        v = 0.5 * (lo + hi)
+        if _sn_drag_force(np.array([0.0, 0.0, v]), d)[2] > m * G:
+            hi = v
+        else:
+            lo = v
+    return 0.5 * (lo + hi)
+
+
+def pin_sn_terminal_velocity(orc):
+    mesh = MeshParams(n=(8, 8, 8), L=(0.1, 0.1, 0.1), rho_f=RHO_F, rho_p=RHO_P, mu_f=MU_F,
+                      g=(0.0, 0.0, -G), drag=1)
+    U = np.zeros(mesh.field_shape)
+    for d, measured in ((100e-6, None), (200e-6, 0.72), (400e-6, 1.62)):
+        tau = _stokes_tau(d)
+        _, up, _ = orc.run(mesh, U, np.array([[0.05, 0.05, 0.05]]), np.zeros((1, 3)),
+                           np.array([d]), tau / 8, 400)
+        v = _sn_settling_speed(d)
+        assert abs(-up[0, 2] - v) <= 1e-9 * v, f"SN settling speed d={d}: {up[0, 2]} vs {v}"
+        assert up[0, 0] == 0.0 and up[0, 1] == 0.0
+        if measured is not None:
+            # fall speeds of small raindrops measured in still air
+            # (Gunn and Kinzer 1949): 72 cm/s at 0.2 mm, 162 cm/s at 0.4 mm
+            assert abs(v - measured) <= 0.05 * measured, f"SN vs measured d={d}: {v}"
+
+
+def pin_sn_force(orc):
+    mesh = MeshParams(n=(8, 8, 8), L=(0.1, 0.1, 0.1), rho_f=RHO_F, rho_p=RHO_P, mu_f=MU_F,
+                      g=(0.0, 0.0, -G), drag=1)
+    uf = np.array([0.7, -0.4, 0.2])
+    U = np.empty(mesh.field_shape)
+    for a in range(3):
+        U[a] = uf[a]
+    for d, v0 in ((60e-6, np.array([-0.5, 0.3, 1.1])), (250e-6, np.array([1.5, 0.1, -2.0]))):
+        tau = _stokes_tau(d)
+        dt = 1e-7 * tau
+        _, up, _ = orc.run(mesh, U, np.array([[0.05, 0.05, 0.05]]), v0[None, :],
+                           np.array([d]), dt, 1)
+        m = RHO_P * math.pi * d ** 3 / 6.0
+        want = _sn_drag_force(uf - v0, d) / m + np.array(mesh.g)
+        got = (up[0] - v0) / dt
+        assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max(), \
+            f"SN acceleration d={d}: {got} vs {want}"
+
+
+# ---------------------------------------------------------------------------
 # deposit
 # ---------------------------------------------------------------------------
-def _conservation_case(orc, g):
+def _conservation_case(orc, g, drag=0):
     rng = np.random.default_rng(18)
     mesh = MeshParams(n=(16, 12, 8), L=(0.1, 0.06, 0.05), g=g, rho_p=RHO_P, mu_f=MU_F,
-                      parcel_weight=3.0)
+                      parcel_weight=3.0, drag=drag)
     U = _tg_field(mesh, rng)
     P = 1500
     x0 = rng.random((P, 3)) * np.array(mesh.L)
@@ -287,6 +357,8 @@ def pin_conservation(orc):
     assert np.all(np.abs(resid) <= 1e-12 * scale), f"momentum balance {resid / scale}"
     resid, scale = _conservation_case(orc, (0.0, 0.0, 0.0))
     assert np.all(np.abs(resid) <= 1e-12 * scale), f"deposit = -d(momentum) {resid / scale}"
+    resid, scale = _conservation_case(orc, (0.0, 0.0, -9.81), drag=1)
+    assert np.all(np.abs(resid) <= 1e-12 * scale), f"momentum balance, SN {resid / scale}"
 
 
 def pin_start_cell_deposit(orc):
@@ -326,15 +398,16 @@ def pin_rotating_field(orc):
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
-def _adjoint_case():
+def _adjoint_case(drag=0):
     rng = np.random.default_rng(20)
     mesh = MeshParams(n=(8, 8, 8), L=(0.01, 0.01, 0.01), rho_p=RHO_P, mu_f=MU_F,
-                      parcel_weight=2.0)
+                      parcel_weight=2.0, drag=drag)
     U = _tg_field(mesh, rng, noise=0.3)
     P = 6
     x0 = rng.random((P, 3)) * 0.01
     up0 = rng.normal(0, 0.3, size=(P, 3))
-    d = np.exp(rng.normal(math.log(30e-6), 0.3, size=P))
+    # larger droplets for Schiller-Naumann so that f - 1 is of order one
+    d = np.exp(rng.normal(math.log(30e-6 if drag == 0 else 90e-6), 0.3, size=P))
     return mesh, U, x0, up0, d
 
 
@@ -348,7 +421,15 @@ def _loss_and_cells(orc, mesh, U, x0, up0, d, dt, nsteps, T):
 
 
 def pin_adjoint_fd(orc):
-    mesh, U, x0, up0, d = _adjoint_case()
+    _adjoint_fd(orc, 0)
+
+
+def pin_adjoint_fd_sn(orc):
+    _adjoint_fd(orc, 1)
+
+
+def _adjoint_fd(orc, drag):
+    mesh, U, x0, up0, d = _adjoint_case(drag)
     dt, nsteps = 2e-4, 6
     L0, S, cells = _loss_and_cells(orc, mesh, U, x0, up0, d, dt, nsteps, 0.0)
     rng = np.random.default_rng(21)
@@ -477,7 +558,8 @@ ALL_PINS = [
     pin_cell_brute_force, pin_wrap, pin_interp_cell_centre, pin_interp_affine,
     pin_interp_shift, pin_interp_ngp, pin_interp_transpose, pin_closed_form_uniform,
     pin_terminal_velocity, pin_first_order, pin_conservation, pin_start_cell_deposit,
-    pin_rotating_field, pin_adjoint_fd, pin_ec_conservative, pin_ec_exact_histories,
+    pin_rotating_field, pin_adjoint_fd, pin_adjoint_fd_sn, pin_sn_terminal_velocity,
+    pin_sn_force, pin_ec_conservative, pin_ec_exact_histories,
     pin_two_way_relaxation,
 ]
 

@@ -84,7 +84,32 @@ MUTANTS = {
     "adjoint: dm/dd factor":
         ("mbar * 3.0 * mass / d[p]", "mbar * 2.0 * mass / d[p]"),
     "adjoint: dtau/dd factor":
-        ("taubar * 2.0 * tau / d[p]", "taubar * tau / d[p]"),
+        ("tausbar * 2.0 * tau_s / d[p]", "tausbar * tau_s / d[p]"),
+    "Schiller-Naumann exponent":
+        ("0.15 * pow(slip_reynolds(m, d, slip), 0.687)", "0.15 * pow(slip_reynolds(m, d, slip), 0.786)"),
+    "Schiller-Naumann coefficient":
+        ("1.0 + 0.15 * pow(", "1.0 + 0.015 * pow("),
+    "Schiller-Naumann Reynolds number with the radius":
+        ("m->rho_f * s * d / m->mu_f", "m->rho_f * s * 0.5 * d / m->mu_f"),
+    "Schiller-Naumann Reynolds number without the fluid density":
+        ("m->rho_f * s * d / m->mu_f", "s * d / m->mu_f"),
+    "Schiller-Naumann Reynolds number from one slip component":
+        ("double s = sqrt(slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2]);",
+         "double s = fabs(slip[0]);"),
+    "Schiller-Naumann factor multiplies the response time":
+        ("double tau = or_tau(m, d) / or_drag_factor(m, d, slip);",
+         "double tau = or_tau(m, d) * or_drag_factor(m, d, slip);"),
+    "Schiller-Naumann slip from the particle velocity alone":
+        ("double slip[3] = {ufp[0] - up[0], ufp[1] - up[1], ufp[2] - up[2]};",
+         "double slip[3] = {-up[0], -up[1], -up[2]};"),
+    "adjoint: Schiller-Naumann slip cotangent sign":
+        ("ufbar[a] += sbar;", "ufbar[a] -= sbar;"),
+    "adjoint: Schiller-Naumann diameter term dropped":
+        ("if (Re > 0.0) db += Rebar * Re / d[p];", ";"),
+    "adjoint: Schiller-Naumann factor left out of the Stokes cotangent":
+        ("double tausbar = taubar / f;", "double tausbar = taubar;"),
+    "adjoint: Schiller-Naumann derivative exponent":
+        ("pow(Re, 0.687 - 1.0)", "pow(Re, 0.687)"),
     "extrapolator-corrector: corrector sign":
         ("double correction = S_last[i] - ext_prev[i];", "double correction = S_last[i] + ext_prev[i];"),
     "extrapolator-corrector: linear coefficients swapped":
