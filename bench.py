@@ -1,7 +1,7 @@
 """Benchmark of the per-particle time step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tg128] [--form fp32_local]
-                [--no-fp64] [--no-adjoint] [--no-scale] [--no-cpu]
+                [--drag stokes] [--no-fp64] [--no-sn] [--no-adjoint] [--no-scale] [--no-cpu]
 
 A step is one pass of the whole hot path (gather, integrate, deposit,
 relocate and re-bin) over every particle of the workload.  Inputs are
@@ -9,7 +9,8 @@ seeded synthetic data resident in HBM before the timed region starts; K
 steps are timed with events on the stream the kernels run on, bracketed by
 device synchronisations.  Prints one JSON line with the whole-job
 particle-steps/s, the step kernel's roofline figures, and beside them: the
-FP64 form on the same workload, forward+adjoint throughput (64^3, 1e6
+FP64 form on the same workload, the same run with Schiller-Naumann drag,
+forward+adjoint throughput (64^3, 1e6
 particles, checkpoints every 20 steps), the 1.4e9-particle 512^3 run with
 the field update on a second stream, and the FP64 oracle timed on this
 host's cores on a bounded sample of the workload.
@@ -39,9 +40,10 @@ def algorithmic_bytes(form, particles, items, E=8):
     return particles * per_particle + items * (tile + deposit), per_particle, tile + deposit
 
 
-def make_tracker(pkg, w, form):
+def make_tracker(pkg, w, form, drag="stokes"):
     return pkg.Tracker(w.n, w.L, w.P, form=form, chunk_edge=w.chunk_edge, rho_f=w.rho_f,
-                       mu_f=w.mu_f, g=w.g, rho_p=w.rho_p, parcel_weight=w.parcel_weight)
+                       mu_f=w.mu_f, g=w.g, rho_p=w.rho_p, parcel_weight=w.parcel_weight,
+                       drag=drag)
 
 
 def inject_host(t, w):
@@ -85,12 +87,12 @@ def measured_traffic(workload, form):
     return float(rec["hbm_bytes_per_launch"])
 
 
-def roofline(form, w, kernel_ms, launches, items):
+def roofline(form, w, kernel_ms, launches, items, drag="stokes"):
     bytes_launch, per_p, per_item = algorithmic_bytes(form, w.P, items, w.chunk_edge)
     avg_s = kernel_ms / max(launches, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, form),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, form) if drag == "stokes" else None,
             "kernel": "k_step", "avg_kernel_ms": avg_s * 1e3, "bytes_per_launch": bytes_launch,
             "model": f"{per_p} B/particle + {per_item} B/work item, {items} items"}
 
@@ -111,8 +113,8 @@ def time_steps(torch, t, U, dt, steps, warmup):
     return e0.elapsed_time(e1), kernel_ms, launches
 
 
-def leg_forward(pkg, torch, np, w, form, steps, warmup):
-    t = make_tracker(pkg, w, form)
+def leg_forward(pkg, torch, np, w, form, steps, warmup, drag="stokes"):
+    t = make_tracker(pkg, w, form, drag)
     if w.P > 50_000_000:
         inject_device(t, w)   # too many to draw on the host in time
     else:
@@ -203,7 +205,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tg128")
     ap.add_argument("--form", default="fp32_local")
+    ap.add_argument("--drag", default="stokes", choices=["stokes", "schiller_naumann"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form leg")
+    ap.add_argument("--no-sn", action="store_true", help="skip the Schiller-Naumann leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1.4e9-particle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -234,10 +238,12 @@ def main():
 
     w = synth.get(args.workload)
     steps = args.steps if args.steps is not None else w.nsteps
-    res = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup)
+    res = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup, args.drag)
     value = w.P * steps / (res["ms"] / 1e3)
+    form_name = {"fp64": "FP64 form", "fp32_local": "FP32 chunk-local form",
+                 "fp32": "FP32 form"}[args.form]
     out = {
-        "metric": "particle-steps/s on 1 MI355X (fwd), FP32 chunk-local form",
+        "metric": f"particle-steps/s on 1 MI355X (fwd), {form_name}",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -250,21 +256,27 @@ def main():
         "dtype": "f64" if args.form == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": list(w.n), "particles": w.P, "dt": w.dt,
-                   "form": args.form, "chunk_edge": w.chunk_edge,
+                   "form": args.form, "chunk_edge": w.chunk_edge, "drag": args.drag,
                    "source_accumulation": "f32" if args.form == "fp32" else "f64",
                    "parallelism": "single GPU"},
         "roofline": roofline(args.form, w, res["kernel_ms"], res["launches"],
-                             res["stats"]["items"]),
+                             res["stats"]["items"], args.drag),
         "step_kernel_share": res["kernel_ms"] / res["ms"],
         "last_step_movers": res["stats"]["movers"],
         "repacks": res["stats"]["repacks"],
     }
     if not args.no_fp64 and args.form != "fp64":
-        r64 = leg_forward(pkg, torch, np, w, "fp64", steps, args.warmup)
+        r64 = leg_forward(pkg, torch, np, w, "fp64", steps, args.warmup, args.drag)
         out["fp64_form"] = {"value": w.P * steps / (r64["ms"] / 1e3),
                             "ms_per_step": r64["ms"] / steps,
                             "avg_kernel_ms": r64["kernel_ms"] / max(r64["launches"], 1)}
         out["speedup_vs_fp64_form"] = value / out["fp64_form"]["value"]
+    if not args.no_sn and args.drag == "stokes":
+        rsn = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup, "schiller_naumann")
+        out["schiller_naumann"] = {
+            "value": w.P * steps / (rsn["ms"] / 1e3), "ms_per_step": rsn["ms"] / steps,
+            "roofline": roofline(args.form, w, rsn["kernel_ms"], rsn["launches"],
+                                 rsn["stats"]["items"], "schiller_naumann")}
     if not args.no_adjoint:
         out["fwd_adjoint"] = leg_adjoint(pkg, torch, np, synth)
     if not args.no_scale:

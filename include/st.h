@@ -14,7 +14,10 @@
  *      Sec. 2.5);
  *   2. integrates m du_p/dt = m (u_f - u_p)/tau + m g with semi-implicit
  *      Euler (drag implicit, gravity explicit, position with the new
- *      velocity; Sec. 2.5), tau = rho_p d^2 / (18 mu_f) (Stokes drag);
+ *      velocity; Sec. 2.5), tau = rho_p d^2 / (18 mu_f) (Stokes drag), or
+ *      tau divided by the Schiller-Naumann factor 1 + 0.15 Re^0.687,
+ *      Re = rho_f |u_f - u_p| d / mu_f, taken from the slip at the start of
+ *      the step (Sec. 2.1, drag force);
  *   3. moves the particle (periodic wrap) and re-bins it into its new cell
  *      and 8^3-cell chunk;
  *   4. deposits the reacting momentum, minus the drag impulse
@@ -72,17 +75,24 @@ typedef enum {
     ST_FORM_FP32 = 2
 } st_form;
 
+typedef enum {
+    ST_DRAG_STOKES = 0,           /* f = 1 */
+    ST_DRAG_SCHILLER_NAUMANN = 1  /* f = 1 + 0.15 Re^0.687 (paper Sec. 2.1) */
+} st_drag;
+
 typedef struct {
     int32_t n[3];          /* cells per axis; each a multiple of chunk_edge */
     int32_t chunk_edge;    /* cells per chunk edge: 2, 4 or 8 */
     double  L[3];          /* domain extent per axis [m]; origin at 0; periodic */
-    double  rho_f;         /* fluid density [kg/m^3] (kept for the record) */
+    double  rho_f;         /* fluid density [kg/m^3], >= 0 (Reynolds number) */
     double  mu_f;          /* fluid dynamic viscosity [Pa s], > 0 */
     double  g[3];          /* gravitational acceleration [m/s^2] */
     double  rho_p;         /* particle material density [kg/m^3], > 0 */
     double  parcel_weight; /* droplets per parcel (paper Sec. 3.2), > 0 */
     int32_t form;          /* an st_form */
     int32_t interp;        /* 0 = trilinear (default), 1 = nearest grid point */
+    int32_t drag;          /* an st_drag */
+    int32_t reserved;      /* must be 0 */
     int64_t capacity;      /* maximum number of particles, >= 1 */
 } st_mesh_desc;
 

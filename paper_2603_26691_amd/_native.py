@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "ST_OK", 1: "ST_ERR_INVALID", 2: "ST_ERR_OOM", 3: "ST_ERR_DEV
                 4: "ST_ERR_STATE", 5: "ST_ERR_CAPACITY"}
 FORMS = {"fp64": 0, "fp32_local": 1, "fp32": 2}
 INTERPS = {"trilinear": 0, "ngp": 1}
+DRAGS = {"stokes": 0, "schiller_naumann": 1}
 
 
 class MeshDesc(ctypes.Structure):
@@ -34,6 +35,8 @@ class MeshDesc(ctypes.Structure):
         ("parcel_weight", ctypes.c_double),
         ("form", ctypes.c_int32),
         ("interp", ctypes.c_int32),
+        ("drag", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("capacity", ctypes.c_int64),
     ]
 

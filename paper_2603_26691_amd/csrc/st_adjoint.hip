@@ -12,6 +12,12 @@
 //   taubar = wbar . (u_p + dt g - u_p') / D
 //   Ubar[corner k] += w_k ufbar,   xbar = xbar' + sum_k grad w_k (U_k . ufbar)
 //   dbar  += taubar 2 tau / d + mbar 3 m / d
+// With Schiller-Naumann drag tau is tau_s / f, f = 1 + 0.15 Re^0.687 of the
+// start-of-step slip s = u_f - u_p, Re = (rho_f / mu_f) d |s|; then
+//   Rebar  = -taubar (tau / f) 0.15 0.687 Re^-0.313
+//   ufbar += Rebar Re s / |s|^2,  ubar -= Rebar Re s / |s|^2
+//   dbar  += (taubar / f) 2 tau_s / d + Rebar Re / d + mbar 3 m / d
+// (zero slip contributes no Re term).
 // The cell c0 and the periodic wrap are piecewise constant (zero derivative).
 //
 // Checkpoints of the particle store are kept every `tape_every` taped steps;
@@ -134,7 +140,12 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
             for (int comp = 0; comp < 3; ++comp) uf[comp] += w[k] * (double)tile[comp * S3 + tc[k]];
 
         // forward quantities of the step
-        const double tau = p.tau_coef * dp * dp;
+        const double tau_s = p.tau_coef * dp * dp;
+        const double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
+        const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
+        const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
+        const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
+        const double tau = tau_s / f;
         const double mass = p.mass_coef * dp * dp * dp;
         const double D = tau + dt;
         double upn[3];
@@ -157,6 +168,15 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
             taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]) / D;
             ub[ax] = -mass * Jbar + tau / D * wbar;
         }
+        double Rebar = 0.0;
+        if (Re > 0.0) {
+            Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
+            for (int ax = 0; ax < 3; ++ax) {
+                const double sb = Rebar * Re * slip[ax] / s2;
+                ufb[ax] += sb;
+                ub[ax] -= sb;
+            }
+        }
         for (int k = 0; k < nk; ++k) {
             double dot = 0.0;
             for (int comp = 0; comp < 3; ++comp) {
@@ -174,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
             a.xb[3 * id + ax] = xb[ax];
             a.ub[3 * id + ax] = ub[ax];
         }
-        a.db[id] += taubar * 2.0 * tau / dp + mbar * 3.0 * mass / dp;
+        a.db[id] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {

@@ -107,6 +107,10 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
         return bad("material constants must be finite and > 0");
     if (d.form < 0 || d.form > 2) return bad("unknown form");
     if (d.interp < 0 || d.interp > 1) return bad("unknown interpolation");
+    if (d.drag < 0 || d.drag > 1) return bad("unknown drag law");
+    if (d.reserved != 0) return bad("reserved must be 0");
+    if (d.drag == ST_DRAG_SCHILLER_NAUMANN && !(d.rho_f >= 0))
+        return bad("rho_f must be >= 0 for Schiller-Naumann drag");
     if (d.capacity < 1) return bad("capacity must be >= 1");
     const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
     if (ncell > ((int64_t)1 << 34)) return bad("mesh too large");
@@ -120,6 +124,7 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     memset(&p, 0, sizeof p);
     p.E = E;
     p.interp = d.interp;
+    p.drag = d.drag;
     for (int a = 0; a < 3; ++a) {
         p.n[a] = d.n[a];
         p.nc[a] = d.n[a] / E;
@@ -132,6 +137,7 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     p.inv_V = 1.0 / (p.h[0] * p.h[1] * p.h[2]);
     p.tau_coef = d.rho_p / (18.0 * d.mu_f);
     p.mass_coef = d.parcel_weight * d.rho_p * kPi / 6.0;
+    p.re_coef = d.rho_f / d.mu_f;
 
     c->C = p.C;
     c->cap = d.capacity;

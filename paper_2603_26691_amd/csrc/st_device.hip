@@ -360,11 +360,21 @@ struct StepArgs {
     T g_dt[3];               // g dt
     T mass_coef;             // w rho_p pi / 6
     T inv_V;                 // 1 / cell volume
+    T re2_coef;              // (rho_f / mu_f)^2: Re^2 = re2_coef d^2 |u_f - u_p|^2
 };
 
 // reciprocal: the hardware's (1 ulp) in binary32, a division in binary64
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Re^0.687 from Re^2 (no square root): 2^(0.3435 log2 Re^2) with the
+// hardware's base-2 logarithm and exponential in binary32, pow in binary64.
+// Re^2 = 0 gives 0 (log2 0 = -inf).
+__device__ __forceinline__ float sn_re_pow(float re2)
+{
+    return __builtin_amdgcn_exp2f(0.3435f * __builtin_amdgcn_logf(re2));
+}
+__device__ __forceinline__ double sn_re_pow(double re2) { return pow(re2, 0.3435); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD walks a contiguous range of work items (neighbouring chunks share
@@ -426,7 +436,7 @@ __device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, i
     }
 }
 
-template <class T, class A, int E, int INTERP>
+template <class T, class A, int E, int INTERP, int DRAG>
 __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
 {
     constexpr int S = E + 2;            // tile edge with the halo
@@ -552,7 +562,14 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             //   u_p' = (tau u_p + dt u_f + tau dt g) / (tau + dt)
             // written as the velocity change, which keeps its relative
             // accuracy in binary32:  u_p' - u_p = dt (u_f - u_p + tau g) / (tau + dt)
-            const T tau = a.tau_coef * dp * dp;
+            T tau = a.tau_coef * dp * dp;
+            if (DRAG == 1) {
+                // Schiller-Naumann: tau / (1 + 0.15 Re^0.687), Re from the
+                // slip at the start of the step
+                const T sx = uf[0] - up[0], sy = uf[1] - up[1], sz = uf[2] - up[2];
+                const T re2 = a.re2_coef * (dp * dp) * (sx * sx + sy * sy + sz * sz);
+                tau = tau * recip(T(1) + T(0.15) * sn_re_pow(re2));
+            }
             const T rD = dt * recip(tau + dt);
             T upn[3], xn[3];
             for (int ax = 0; ax < 3; ++ax) {
@@ -1228,18 +1245,25 @@ hipError_t dispatch(st_ctx *c, F &&f)
     }
 }
 
-template <class T, class A, int E, int I>
+template <class T, class A, int E, int I, int D>
 hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<T, A, E, I>), dim3(c->max_items), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(c->max_items), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+template <class T, class A, int E, int I>
+hipError_t launch_step_d(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+{
+    return c->prm.drag == 1 ? launch_step_t<T, A, E, I, 1>(c, a, s)
+                            : launch_step_t<T, A, E, I, 0>(c, a, s);
 }
 
 template <class T, class A, int E>
 hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
 {
-    return c->prm.interp == 1 ? launch_step_t<T, A, E, 1>(c, a, s)
-                              : launch_step_t<T, A, E, 0>(c, a, s);
+    return c->prm.interp == 1 ? launch_step_d<T, A, E, 1>(c, a, s)
+                              : launch_step_d<T, A, E, 0>(c, a, s);
 }
 
 template <class T>
@@ -1357,6 +1381,7 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         for (int ax = 0; ax < 3; ++ax) a.g_dt[ax] = (T)(c->prm.g[ax] * dt);
         a.mass_coef = (T)c->prm.mass_coef;
         a.inv_V = (T)c->prm.inv_V;
+        a.re2_coef = (T)(c->prm.re_coef * c->prm.re_coef);
         hipEvent_t ev[2] = {nullptr, nullptr};
         if (c->timing) {
             for (int k = 0; k < 2; ++k) {

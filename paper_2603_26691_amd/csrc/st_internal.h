@@ -52,6 +52,8 @@ struct Params {
     int32_t nc[3];         // chunks per axis
     int32_t E;             // chunk edge
     int32_t interp;        // 0 trilinear, 1 nearest grid point
+    int32_t drag;          // 0 Stokes, 1 Schiller-Naumann
+    int32_t pad_;
     int64_t C;             // chunks
     double L[3];           // domain extent
     double h[3];           // cell widths
@@ -60,6 +62,7 @@ struct Params {
     double g[3];
     double tau_coef;       // rho_p / (18 mu_f): tau = tau_coef d^2
     double mass_coef;      // w rho_p pi / 6:    m = mass_coef d^3
+    double re_coef;        // rho_f / mu_f:      Re = re_coef d |u_f - u_p|
 };
 
 // Flags and counters on the device (one int32 each).  F_OVERFLOW and

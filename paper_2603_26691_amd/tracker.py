@@ -25,12 +25,12 @@ class Tracker:
 
     n: cells per axis (multiples of chunk_edge); L: domain extent [m];
     form: "fp64", "fp32_local" or "fp32"; interp: "trilinear" or "ngp";
-    capacity: maximum number of particles.
+    drag: "stokes" or "schiller_naumann"; capacity: maximum number of particles.
     """
 
     def __init__(self, n, L, capacity, form="fp32_local", interp="trilinear", chunk_edge=8,
                  rho_f=1.2, mu_f=1.8e-5, g=(0.0, 0.0, -9.81), rho_p=1000.0,
-                 parcel_weight=1.0, device=0):
+                 parcel_weight=1.0, drag="stokes", device=0):
         d = N.MeshDesc()
         d.n[:] = [int(v) for v in n]
         d.chunk_edge = int(chunk_edge)
@@ -42,12 +42,14 @@ class Tracker:
         d.parcel_weight = float(parcel_weight)
         d.form = N.FORMS[form] if isinstance(form, str) else int(form)
         d.interp = N.INTERPS[interp] if isinstance(interp, str) else int(interp)
+        d.drag = N.DRAGS[drag] if isinstance(drag, str) else int(drag)
         d.capacity = int(capacity)
         self.desc = d
         self.form = form
         self.n = tuple(int(v) for v in n)
         self.L = tuple(float(v) for v in L)
         self.device = torch.device("cuda", device)
+        self._taped = []   # fields borrowed by taped steps
         ctx = ctypes.c_void_p()
         st = N.lib().st_create_mesh(ctypes.byref(d), int(device), ctypes.byref(ctx))
         if st != N.ST_OK:
@@ -107,11 +109,15 @@ class Tracker:
         return v.value
 
     def step(self, u, dt, nsub=1, tape=0):
-        """One step of dt with the device field u [3, nz, ny, nx] (kept alive by the caller)."""
+        """One step of dt with the device field u [3, nz, ny, nx].  A taped
+        step borrows u until backward() or tape_clear(); the tracker holds a
+        reference to it until then."""
         assert u.is_cuda and u.dtype == self.field_dtype and u.is_contiguous()
         assert tuple(u.shape) == self.field_shape
         N.check(N.lib().st_step(self.ctx, _dptr(u), float(dt), int(nsub), int(tape), _stream()),
                 self.ctx)
+        if tape:
+            self._taped.append(u)
 
     def sources(self, reset=False):
         """Time-integrated momentum source, float64 [3, nz, ny, nx] on the device."""
@@ -143,10 +149,12 @@ class Tracker:
         dd = torch.zeros((self.count(),), dtype=torch.float64, device=self.device)
         N.check(N.lib().st_backward(self.ctx, _dptr(lam), _dptr(dU), _dptr(dd), _stream()),
                 self.ctx)
+        self._taped = []
         return dU, dd
 
     def tape_clear(self):
         N.check(N.lib().st_tape_clear(self.ctx), self.ctx)
+        self._taped = []
 
     def run_coupled(self, u0, cs, dt, timed=True):
         """Coupled run with the rotating field; returns (field_ms, step_ms, total_ms)."""

@@ -18,15 +18,18 @@ def workload(name="tg32", **kw):
     return dataclasses.replace(w, **kw) if kw else w
 
 
-def oracle_mesh(w, interp=0):
-    return MeshParams(interp=interp, **w.mesh_kwargs())
+DRAGS = ("stokes", "schiller_naumann")   # oracle drag codes 0, 1
 
 
-def tracker(w, form, capacity=None, interp="trilinear"):
+def oracle_mesh(w, interp=0, drag="stokes"):
+    return MeshParams(interp=interp, drag=DRAGS.index(drag), **w.mesh_kwargs())
+
+
+def tracker(w, form, capacity=None, interp="trilinear", drag="stokes"):
     import paper_2603_26691_amd as pkg
     return pkg.Tracker(w.n, w.L, capacity or max(w.P, 1), form=form, interp=interp,
                        chunk_edge=w.chunk_edge, rho_f=w.rho_f, mu_f=w.mu_f, g=w.g,
-                       rho_p=w.rho_p, parcel_weight=w.parcel_weight)
+                       rho_p=w.rho_p, parcel_weight=w.parcel_weight, drag=drag)
 
 
 def fields(w, form):

@@ -69,13 +69,15 @@ def _desc(N, **kw):
     d.n[:] = kw.get("n", (16, 16, 16))
     d.chunk_edge = kw.get("chunk_edge", 8)
     d.L[:] = kw.get("L", (0.1, 0.1, 0.1))
-    d.rho_f = 1.2
+    d.rho_f = kw.get("rho_f", 1.2)
     d.mu_f = kw.get("mu_f", 1.8e-5)
     d.g[:] = (0.0, 0.0, -9.81)
     d.rho_p = kw.get("rho_p", 1000.0)
     d.parcel_weight = kw.get("w", 1.0)
     d.form = kw.get("form", 1)
     d.interp = kw.get("interp", 0)
+    d.drag = kw.get("drag", 0)
+    d.reserved = kw.get("reserved", 0)
     d.capacity = kw.get("capacity", 1000)
     return d
 
@@ -84,7 +86,8 @@ def _desc(N, **kw):
     dict(chunk_edge=3), dict(chunk_edge=16), dict(n=(12, 16, 16)), dict(n=(16, 16, 0)),
     dict(L=(0.1, -1.0, 0.1)), dict(L=(0.1, float("nan"), 0.1)), dict(mu_f=0.0),
     dict(rho_p=-1.0), dict(w=0.0), dict(form=7), dict(interp=2), dict(capacity=0),
-    dict(capacity=1 << 40),
+    dict(capacity=1 << 40), dict(drag=2), dict(drag=-1), dict(reserved=1),
+    dict(drag=1, rho_f=-1.0), dict(drag=1, rho_f=float("nan")),
 ])
 def test_create_rejects_bad_descriptor_on_host(N, bad):
     ctx = ctypes.c_void_p()

@@ -32,12 +32,12 @@ def orc():
     return load_oracle()
 
 
-def _run_lockstep(orc, w, form, nsteps=4, interp=0, nsub=1, dt=None):
-    t = tracker(w, form, interp="ngp" if interp else "trilinear")
+def _run_lockstep(orc, w, form, nsteps=4, interp=0, nsub=1, dt=None, drag="stokes"):
+    t = tracker(w, form, interp="ngp" if interp else "trilinear", drag=drag)
     x, up, d = w.particles()
     t.inject(x, up, d)
     Udev, Uor = fields(w, form)
-    out = lockstep_check(t, orc, oracle_mesh(w, interp), Udev, Uor, dt or w.dt, nsteps,
+    out = lockstep_check(t, orc, oracle_mesh(w, interp, drag), Udev, Uor, dt or w.dt, nsteps,
                          TOL[form], nsub=nsub)
     print(form, w.name, out)
     t.close()
@@ -49,6 +49,21 @@ def test_lockstep_tg32(orc, form):
     # 32^3 mesh (64 chunks), 20000 droplets, Taylor-Green field with noise
     w = workload("tg32", P=20000, noise=0.1)
     _run_lockstep(orc, w, form, nsteps=4)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_lockstep_schiller_naumann(orc, form):
+    # Schiller-Naumann drag with droplets of median 60 um, so that the slip
+    # Reynolds number (droplets start at rest in a 1 m/s field) is 1 to 10
+    w = workload("tg32", P=20000, noise=0.1, d_median=60e-6)
+    out = _run_lockstep(orc, w, form, nsteps=4, drag="schiller_naumann")
+    assert out["compared"] > 0
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_lockstep_schiller_naumann_ngp_substeps(orc, form):
+    w = workload("tg32", P=10000, noise=0.1, d_median=60e-6)
+    _run_lockstep(orc, w, form, nsteps=2, interp=1, nsub=3, dt=3e-4, drag="schiller_naumann")
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32_local"])
