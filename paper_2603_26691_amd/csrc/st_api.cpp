@@ -48,7 +48,7 @@ void free_all(st_ctx *c)
 {
     for (int b = 0; b < 2; ++b)
         for (int k = 0; k < 8; ++k) (void)hipFree(c->store[b][k]);
-    for (int k = 0; k < 10; ++k) (void)hipFree(c->mov[k]);
+    for (int k = 0; k < 2; ++k) (void)hipFree(c->mov[k]);
     void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->cursor,
                        c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
                        c->scan_tmp, c->flags, c->src, c->stage64, c->fieldbuf[0],
@@ -171,8 +171,9 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     A(&c->base, (size_t)(C + 1) * 8);
     A(&c->room, (size_t)C * 4);
     A(&c->cnt, (size_t)C * 4);
-    for (int k = 0; k < 7; ++k) A(&c->mov[k], (size_t)c->mcap * c->tsize);
-    for (int k = 7; k < 10; ++k) A(&c->mov[k], (size_t)c->mcap * 4);
+    A(&c->mov[0], (size_t)c->mcap * (c->tsize == 8 ? sizeof(st::MoverRec<double>)
+                                                   : sizeof(st::MoverRec<float>)));
+    A(&c->mov[1], (size_t)c->mcap * 4);
     A(&c->out_cnt, (size_t)C * 4);
     A(&c->in_cnt, (size_t)C * 4);
     A(&c->cursor, (size_t)C * 4);

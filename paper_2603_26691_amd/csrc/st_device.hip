@@ -7,10 +7,12 @@
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
 //             the chunk's cells, write every particle back in place, collect
-//             the chunk crossers ("movers") in LDS and emit them with one
-//             global reservation per workgroup, and flush the accumulator
-//             with one read-modify-write (or one atomic, for chunks split
-//             over several items) per cell;
+//             the chunk crossers ("movers") in LDS by direction and emit
+//             them as whole records, with one atomic instruction for all of
+//             a workgroup's reservations (mover list, vacated slots, one
+//             arrival count per neighbouring chunk), and flush the
+//             accumulator with one read-modify-write (or one atomic, for
+//             chunks split over several items) per cell;
 //   check     the room check of every chunk (a mover files itself in its
 //             destination chunk's inbox when it is emitted);
 //   fill      one wave per chunk: arrivals and, when the chunk shrank, its
@@ -402,6 +404,19 @@ __device__ __forceinline__ void vst(T *p, const T (&v)[G])
     __builtin_memcpy(q, v, G * sizeof(T));
 }
 
+// base + byte offset: a uniform 64-bit base plus a 32-bit per-lane offset,
+// which the loads and stores take in their scalar-base addressing form
+template <class T>
+__device__ __forceinline__ T *at_byte(T *base, uint32_t byte_off)
+{
+    return (T *)((char *)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ const T *at_byte(const T *base, uint32_t byte_off)
+{
+    return (const T *)((const char *)base + byte_off);
+}
+
 // A mover already written in place (un-rebased offsets, relative to chunk
 // c): records the vacated slot, marks it, copies the particle, re-based
 // onto its destination chunk, into the mover list at m and files m in the
@@ -418,14 +433,7 @@ __device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, i
     V.id[q] = -1 - id;
     a.hole[base + hpos] = (int32_t)(q - base);
     if (m < a.mcap) {
-        a.mv.ox[m] = x;
-        a.mv.oy[m] = y;
-        a.mv.oz[m] = z;
-        a.mv.vx[m] = vx;
-        a.mv.vy[m] = vy;
-        a.mv.vz[m] = vz;
-        a.mv.d[m] = dd;
-        a.mv.id[m] = id;
+        a.mv.rec[m] = MoverRec<T>{x, y, z, vx, vy, vz, dd, id};
         a.mv.dest[m] = (int32_t)cn;
         const int32_t r = atomicAdd(&a.in_cnt[cn], 1);
         // an arrival rank beyond the room means the chunk overflows (the room
@@ -436,8 +444,17 @@ __device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, i
     }
 }
 
+// Staged mover: its slot within the work item (below kSeg, 14 bits), its
+// direction class (0..26 the neighbouring chunks, 27 farther; 5 bits) and its
+// rank within that class (below kMoverStage, 9 bits).
+constexpr int kSlotBits = 14, kDirBits = 5;
+static_assert(kSeg <= (1 << kSlotBits) && kMoverStage <= (1 << (32 - 1 - kSlotBits - kDirBits)),
+              "staged mover fields must fit one int32");
+static_assert(kDirBits * 4 <= 32, "direction classes of a group must fit one uint32");
+
 template <class T, class A, int E, int INTERP, int DRAG>
-__global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
+__global__ void __launch_bounds__(kBlock)
+     k_step(StepArgs<T, A> a)
 {
     constexpr int S = E + 2;            // tile edge with the halo
     constexpr int S3 = S * S * S;
@@ -446,9 +463,10 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     static_assert(kAlign % G == 0, "chunk rooms must hold whole particle groups");
     __shared__ T tile[3 * S3];
     __shared__ A acc[3 * E3];
-    __shared__ int32_t mslot[kMoverStage];
+    __shared__ int32_t mstage[kMoverStage];
     __shared__ int32_t mcount, mbase_sh, hbase_sh;
-    __shared__ int32_t dcount[27], dbase[27];
+    __shared__ int32_t dcount[28], doff[28], dbase[27], nb_room[27];
+    __shared__ int64_t nb_base[27];
 
     const int64_t item = xcd_remap(blockIdx.x, a.grid);
     if (item >= *a.nitems) return;
@@ -466,11 +484,34 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
     const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
     const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
 
-    // stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped; all
-    // of a thread's loads are issued before the first is used
+    // The work item's slots are read in groups of G consecutive slots through
+    // uniform base pointers and 32-bit offsets (at most kSeg).  s0 is a
+    // multiple of G (chunk bases and kSeg are), and a group that runs past s1
+    // stays inside the chunk's room.
+    const int nq = (int)(s1 - s0);
+    const int ngroups = (nq + G - 1) / G;
+    T *const pox = V.ox + s0, *const poy = V.oy + s0, *const poz = V.oz + s0;
+    T *const pvx = V.vx + s0, *const pvy = V.vy + s0, *const pvz = V.vz + s0;
+    const T *const pd = V.d + s0;
+    auto load_group = [&](int gi, T (&X)[G], T (&Y)[G], T (&Z)[G], T (&UX)[G], T (&UY)[G],
+                          T (&UZ)[G], T (&DD)[G]) {
+        const uint32_t ob = (uint32_t)gi * G * (uint32_t)sizeof(T);
+        vld<T, G>(at_byte(pox, ob), X);
+        vld<T, G>(at_byte(poy, ob), Y);
+        vld<T, G>(at_byte(poz, ob), Z);
+        vld<T, G>(at_byte(pvx, ob), UX);
+        vld<T, G>(at_byte(pvy, ob), UY);
+        vld<T, G>(at_byte(pvz, ob), UZ);
+        vld<T, G>(at_byte(pd, ob), DD);
+    };
+
+    // Stage the fluid tile: cells E*c - 1 .. E*c + E per axis, wrapped.  The
+    // main loop is software-pipelined: a group's loads are issued before the
+    // arithmetic of the previous one, and the first group's right after the
+    // tile's loads, so that memory latency overlaps work.
+    constexpr int NT = (3 * S3 + kBlock - 1) / kBlock;
+    T vals[NT];
     {
-        constexpr int NT = (3 * S3 + kBlock - 1) / kBlock;
-        T vals[NT];
         const int ox0 = cx * E - 1, oy0 = cy * E - 1, oz0 = cz * E - 1;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
@@ -491,35 +532,31 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
                 vals[u] = a.u[comp * ncell + ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx];
             }
         }
+    }
+    int gi = threadIdx.x;
+    T X[G], Y[G], Z[G], UX[G], UY[G], UZ[G], DD[G];
+    if (gi < ngroups) load_group(gi, X, Y, Z, UX, UY, UZ, DD);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int t = threadIdx.x + u * kBlock;
-            if (t < 3 * S3) tile[t] = vals[u];
-        }
+    for (int u = 0; u < NT; ++u) {
+        const int t = threadIdx.x + u * kBlock;
+        if (t < 3 * S3) tile[t] = vals[u];
     }
     for (int t = threadIdx.x; t < 3 * E3; t += kBlock) acc[t] = A(0);
+    if (threadIdx.x < 28) dcount[threadIdx.x] = 0;
     if (threadIdx.x == 0) mcount = 0;
     __syncthreads();
 
     const T dt = a.dt;
     const T fe = T(E), inv_e = T(1) / T(E);
-    // groups of G consecutive slots; s0 is a multiple of G (chunk bases and
-    // kSeg are), and a group that runs past s1 stays inside the chunk's room
-    const int64_t ngroups = (s1 - s0 + G - 1) / G;
-    for (int64_t gi = threadIdx.x; gi < ngroups; gi += kBlock) {
-        const int64_t q0 = s0 + gi * G;
-        T X[G], Y[G], Z[G], UX[G], UY[G], UZ[G], DD[G];
-        vld<T, G>(V.ox + q0, X);
-        vld<T, G>(V.oy + q0, Y);
-        vld<T, G>(V.oz + q0, Z);
-        vld<T, G>(V.vx + q0, UX);
-        vld<T, G>(V.vy + q0, UY);
-        vld<T, G>(V.vz + q0, UZ);
-        vld<T, G>(V.d + q0, DD);
-        uint32_t movers = 0;
+    for (; gi < ngroups; gi += kBlock) {
+        T Xn[G], Yn[G], Zn[G], UXn[G], UYn[G], UZn[G], DDn[G];
+        if (gi + kBlock < ngroups) load_group(gi + kBlock, Xn, Yn, Zn, UXn, UYn, UZn, DDn);
+        const uint32_t o = (uint32_t)gi * G;
+        const uint32_t ob = o * (uint32_t)sizeof(T);
+        uint32_t movers = 0, dirs = 0;   // mover bits and 5-bit direction classes
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const bool valid = q0 + k < s1;
+            const bool valid = (int)o + k < nq;
             const T xi[3] = {X[k], Y[k], Z[k]};
             const T up[3] = {UX[k], UY[k], UZ[k]};
             const T dp = DD[k];
@@ -602,128 +639,182 @@ __global__ void __launch_bounds__(kBlock) k_step(StepArgs<T, A> a)
             UX[k] = upn[0];
             UY[k] = upn[1];
             UZ[k] = upn[2];
-            if (valid && mover) movers |= 1u << k;
+            if (valid && mover) {
+                movers |= 1u << k;
+                T tx = xn[0], ty = xn[1], tz = xn[2];
+                const int kx = rebase(tx, fe, inv_e);
+                const int ky = rebase(ty, fe, inv_e);
+                const int kz = rebase(tz, fe, inv_e);
+                const int dir = (abs(kx) <= 1 && abs(ky) <= 1 && abs(kz) <= 1)
+                                    ? (kx + 1) + 3 * (ky + 1) + 9 * (kz + 1) : 27;
+                dirs |= (uint32_t)dir << (kDirBits * k);
+            }
         }
         // slots past s1 in the last group are dead; writing them is harmless
-        vst<T, G>(V.ox + q0, X);
-        vst<T, G>(V.oy + q0, Y);
-        vst<T, G>(V.oz + q0, Z);
-        vst<T, G>(V.vx + q0, UX);
-        vst<T, G>(V.vy + q0, UY);
-        vst<T, G>(V.vz + q0, UZ);
+        vst<T, G>(at_byte(pox, ob), X);
+        vst<T, G>(at_byte(poy, ob), Y);
+        vst<T, G>(at_byte(poz, ob), Z);
+        vst<T, G>(at_byte(pvx, ob), UX);
+        vst<T, G>(at_byte(pvy, ob), UY);
+        vst<T, G>(at_byte(pvz, ob), UZ);
+        // stage the movers with their direction class and rank in it
         while (movers) {
             const int k = __ffs(movers) - 1;
             movers &= movers - 1;
-            const int64_t qc = q0 + k;
             const int j = atomicAdd(&mcount, 1);
             if (j < kMoverStage) {
-                mslot[j] = (int32_t)(qc - base);
+                const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
+                const int rank = atomicAdd(&dcount[dir], 1);
+                mstage[j] = (int32_t)(o + k) | (dir << kSlotBits) |
+                            (rank << (kSlotBits + kDirBits));
             } else {  // more movers than the LDS stage holds: emit directly
                 const int64_t m = atomicAdd(a.nmov, 1);
                 const int64_t h = atomicAdd(&a.out_cnt[c], 1);
-                emit_mover(a, c, base, qc, m, h);
+                emit_mover(a, c, base, s0 + o + k, m, h);
             }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            X[k] = Xn[k];
+            Y[k] = Yn[k];
+            Z[k] = Zn[k];
+            UX[k] = UXn[k];
+            UY[k] = UYn[k];
+            UZ[k] = UZn[k];
+            DD[k] = DDn[k];
         }
     }
     __syncthreads();
 
-    // flush the chunk's accumulated source (loads batched before the stores)
-    if (a.deposit) {
-        constexpr int NF = (3 * E3 + kBlock - 1) / kBlock;
-        A *dst = a.src + c * (3 * E3);
-        if (multi) {
-            for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
-                const A v = acc[t];
-                if (v != A(0)) atomicAdd(dst + t, v);
-            }
-        } else {
-            A old[NF];
+    // Mover reservations, all issued by one wave at once: the workgroup's
+    // slots in the mover list (ordered by direction class, movers farther
+    // than one chunk last, so that the arrivals a destination receives from
+    // this chunk sit in consecutive records), its entries in the chunk's
+    // vacated-slot list, and one arrival-count reservation per neighbouring
+    // destination instead of one per mover, which would serialise on the
+    // counters of crowded chunks.  The movers' state is read in the same
+    // round trip.
+    const int nm = min(mcount, kMoverStage);
+    // The chunk's source cells are read first (a chunk that is one work item
+    // adds its sum to them; one split over several items adds atomically).
+    A *const src_c = a.src + c * (3 * E3);
+    constexpr int NF = (3 * E3 + kBlock - 1) / kBlock;
+    A old[NF];
+    const bool rmw = a.deposit && !multi;
+    if (rmw) {
 #pragma unroll
-            for (int u = 0; u < NF; ++u) {
-                const int t = threadIdx.x + u * kBlock;
-                old[u] = t < 3 * E3 ? dst[t] : A(0);
-            }
+        for (int u = 0; u < NF; ++u) {
+            const int t = threadIdx.x + u * kBlock;
+            old[u] = t < 3 * E3 ? src_c[t] : A(0);
+        }
+    }
+    constexpr int NM = kMoverStage / kBlock;   // staged movers per thread
+    T mx[NM], my[NM], mz[NM], mvx[NM], mvy[NM], mvz[NM], md[NM];
+    int32_t mid[NM];
 #pragma unroll
-            for (int u = 0; u < NF; ++u) {
-                const int t = threadIdx.x + u * kBlock;
-                if (t < 3 * E3) dst[t] = old[u] + acc[t];
+    for (int u = 0; u < NM; ++u) {
+        const int j = threadIdx.x + u * kBlock;
+        if (j < nm) {
+            const int64_t q = s0 + (mstage[j] & ((1 << kSlotBits) - 1));
+            mx[u] = V.ox[q];
+            my[u] = V.oy[q];
+            mz[u] = V.oz[q];
+            mvx[u] = V.vx[q];
+            mvy[u] = V.vy[q];
+            mvz[u] = V.vz[q];
+            md[u] = V.d[q];
+            mid[u] = V.id[q];
+        }
+    }
+    if (nm > 0 && threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int n = lane < 28 ? dcount[lane] : 0;
+        int incl = n;
+        for (int off = 1; off < 32; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (lane >= off) incl += v;
+        }
+        if (lane < 28) doff[lane] = incl - n;
+        // one atomic instruction for all reservations (the counters differ
+        // per lane): lanes 0..26 the arrival counts of the neighbouring
+        // chunks, lane 32 the mover list, lane 33 the vacated-slot list
+        const bool nb = lane < 27 && n > 0;
+        const int64_t dc = chunk_index(p, wrapi(cx + lane % 3 - 1, p.nc[0]),
+                                       wrapi(cy + (lane / 3) % 3 - 1, p.nc[1]),
+                                       wrapi(cz + (lane / 9) % 3 - 1, p.nc[2]));
+        int32_t *ctr = nb ? &a.in_cnt[dc] : lane == 32 ? a.nmov : &a.out_cnt[c];
+        const int add = nb ? n : nm;
+        if (nb || lane == 32 || lane == 33) {
+            const int32_t r = atomicAdd(ctr, add);
+            if (nb) {
+                dbase[lane] = r;
+                nb_base[lane] = V.base[dc];
+                nb_room[lane] = V.room[dc];
             }
+            if (lane == 32) mbase_sh = r;
+            if (lane == 33) hbase_sh = r;
         }
     }
 
-    // Emit the staged movers: one reservation per workgroup in the mover
-    // list and the vacated-slot list, and one arrival-count reservation per
-    // neighbouring destination chunk (the 26 directions) instead of one per
-    // mover, which would serialise on the counters of crowded chunks.
-    const int nm = min(mcount, kMoverStage);
-    if (nm > 0) {
-        constexpr int NM = kMoverStage / kBlock;  // staged movers per thread
-        if (threadIdx.x < 27) dcount[threadIdx.x] = 0;
-        if (threadIdx.x == 0) {
-            mbase_sh = atomicAdd(a.nmov, nm);
-            hbase_sh = atomicAdd(&a.out_cnt[c], nm);
-        }
-        __syncthreads();
-        T mx[NM], my[NM], mz[NM];
-        int32_t mdir[NM], mrank[NM];
-        int64_t mdest[NM];
+    // flush the chunk's accumulated source
+    if (rmw) {
 #pragma unroll
-        for (int u = 0; u < NM; ++u) {
-            const int j = threadIdx.x + u * kBlock;
-            mdir[u] = -1;
-            if (j < nm) {
-                const int64_t q = base + mslot[j];
-                mx[u] = V.ox[q];
-                my[u] = V.oy[q];
-                mz[u] = V.oz[q];
-                const int kx = rebase(mx[u], fe, inv_e);
-                const int ky = rebase(my[u], fe, inv_e);
-                const int kz = rebase(mz[u], fe, inv_e);
-                mdest[u] = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
-                                       wrapi(cz + kz, p.nc[2]));
-                if (abs(kx) <= 1 && abs(ky) <= 1 && abs(kz) <= 1) {
-                    mdir[u] = (kx + 1) + 3 * (ky + 1) + 9 * (kz + 1);
-                    mrank[u] = atomicAdd(&dcount[mdir[u]], 1);
-                } else {  // farther than one chunk: its own reservation
-                    mrank[u] = atomicAdd(&a.in_cnt[mdest[u]], 1);
-                }
-            }
+        for (int u = 0; u < NF; ++u) {
+            const int t = threadIdx.x + u * kBlock;
+            if (t < 3 * E3) src_c[t] = old[u] + acc[t];
         }
-        __syncthreads();
-        if (threadIdx.x < 27 && dcount[threadIdx.x] > 0) {
-            const int dir = threadIdx.x;
-            const int64_t dc = chunk_index(p, wrapi(cx + dir % 3 - 1, p.nc[0]),
-                                           wrapi(cy + (dir / 3) % 3 - 1, p.nc[1]),
-                                           wrapi(cz + dir / 9 - 1, p.nc[2]));
-            dbase[dir] = atomicAdd(&a.in_cnt[dc], dcount[dir]);
+    } else if (a.deposit) {
+        for (int t = threadIdx.x; t < 3 * E3; t += kBlock) {
+            const A v = acc[t];
+            if (v != A(0)) atomicAdd(src_c + t, v);
         }
-        __syncthreads();
+    }
+    if (nm == 0) return;
+    __syncthreads();
+
+    // emit the staged movers into their records and the arrival lists
 #pragma unroll
-        for (int u = 0; u < NM; ++u) {
-            const int j = threadIdx.x + u * kBlock;
-            if (j >= nm) continue;
-            const int64_t q = base + mslot[j];
-            const int64_t m = (int64_t)mbase_sh + j;
-            const int32_t id = V.id[q];
-            V.id[q] = -1 - id;
-            a.hole[base + hbase_sh + j] = mslot[j];
-            if (m < a.mcap) {
-                a.mv.ox[m] = mx[u];
-                a.mv.oy[m] = my[u];
-                a.mv.oz[m] = mz[u];
-                a.mv.vx[m] = V.vx[q];
-                a.mv.vy[m] = V.vy[q];
-                a.mv.vz[m] = V.vz[q];
-                a.mv.d[m] = V.d[q];
-                a.mv.id[m] = id;
-                a.mv.dest[m] = (int32_t)mdest[u];
-                const int32_t r = mdir[u] >= 0 ? dbase[mdir[u]] + mrank[u] : mrank[u];
-                // a rank beyond the room means the chunk overflows (the room
-                // check sees it too); the entry is then never read
-                if (r < V.room[mdest[u]]) a.inbox[V.base[mdest[u]] + r] = (int32_t)m;
-            } else {
-                a.flags[F_OVERFLOW] = a.epoch;
-            }
+    for (int u = 0; u < NM; ++u) {
+        const int j = threadIdx.x + u * kBlock;
+        if (j >= nm) continue;
+        const int32_t w = mstage[j];
+        const int32_t off = w & ((1 << kSlotBits) - 1);
+        const int dir = (w >> kSlotBits) & ((1 << kDirBits) - 1);
+        const int rank = w >> (kSlotBits + kDirBits);
+        const int64_t m = (int64_t)mbase_sh + doff[dir] + rank;
+        // re-base the offsets into the destination chunk
+        const int kx = rebase(mx[u], fe, inv_e);
+        const int ky = rebase(my[u], fe, inv_e);
+        const int kz = rebase(mz[u], fe, inv_e);
+        int64_t dest;
+        int32_t r;
+        int64_t dbas;
+        int32_t droom;
+        if (dir < 27) {   // within the direction's reservation
+            dest = chunk_index(p, wrapi(cx + dir % 3 - 1, p.nc[0]),
+                               wrapi(cy + (dir / 3) % 3 - 1, p.nc[1]),
+                               wrapi(cz + dir / 9 - 1, p.nc[2]));
+            r = dbase[dir] + rank;
+            dbas = nb_base[dir];
+            droom = nb_room[dir];
+        } else {          // farther than one chunk: a reservation of its own
+            dest = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
+                               wrapi(cz + kz, p.nc[2]));
+            r = atomicAdd(&a.in_cnt[dest], 1);
+            dbas = V.base[dest];
+            droom = V.room[dest];
+        }
+        V.id[s0 + off] = -1 - mid[u];
+        a.hole[base + hbase_sh + j] = (int32_t)(s0 + off - base);
+        if (m < a.mcap) {
+            a.mv.rec[m] = MoverRec<T>{mx[u], my[u], mz[u], mvx[u], mvy[u], mvz[u], md[u],
+                                      mid[u]};
+            a.mv.dest[m] = (int32_t)dest;
+            // a rank beyond the room means the chunk overflows (the room
+            // check sees it too); the entry is then never read
+            if (r < droom) a.inbox[dbas + r] = (int32_t)m;
+        } else {
+            a.flags[F_OVERFLOW] = a.epoch;
         }
     }
 }
@@ -761,14 +852,15 @@ template <class T>
 __device__ __forceinline__ void place_mover(const View<T> &V, int64_t dst, const Movers<T> &mv,
                                             int64_t m)
 {
-    V.ox[dst] = mv.ox[m];
-    V.oy[dst] = mv.oy[m];
-    V.oz[dst] = mv.oz[m];
-    V.vx[dst] = mv.vx[m];
-    V.vy[dst] = mv.vy[m];
-    V.vz[dst] = mv.vz[m];
-    V.d[dst] = mv.d[m];
-    V.id[dst] = mv.id[m];
+    const MoverRec<T> r = mv.rec[m];
+    V.ox[dst] = r.ox;
+    V.oy[dst] = r.oy;
+    V.oz[dst] = r.oz;
+    V.vx[dst] = r.vx;
+    V.vy[dst] = r.vy;
+    V.vz[dst] = r.vz;
+    V.d[dst] = r.d;
+    V.id[dst] = r.id;
 }
 
 template <class T>
@@ -972,14 +1064,7 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(RebinArgs<T> a)
          m += (int64_t)gridDim.x * blockDim.x) {
         const int64_t cn = a.mv.dest[m];
         const int64_t dst = a.nbase[cn] + atomicAdd(&a.cursor[cn], 1);
-        W.ox[dst] = a.mv.ox[m];
-        W.oy[dst] = a.mv.oy[m];
-        W.oz[dst] = a.mv.oz[m];
-        W.vx[dst] = a.mv.vx[m];
-        W.vy[dst] = a.mv.vy[m];
-        W.vz[dst] = a.mv.vz[m];
-        W.d[dst] = a.mv.d[m];
-        W.id[dst] = a.mv.id[m];
+        place_mover(W, dst, a.mv, m);
     }
 }
 
@@ -1044,16 +1129,9 @@ __global__ void k_stage(int64_t n, const double *x, const double *up, const doub
             if (!isfinite(v[a])) ok = false;
         if (!isfinite(dd) || !(dd > 0.0)) ok = false;
         const int64_t m = at + i;
-        mv.ox[m] = loc[0];
-        mv.oy[m] = loc[1];
-        mv.oz[m] = loc[2];
-        mv.vx[m] = (T)v[0];
-        mv.vy[m] = (T)v[1];
-        mv.vz[m] = (T)v[2];
-        mv.d[m] = (T)dd;
-        mv.id[m] = (int32_t)(id0 + i);
+        mv.rec[m] = MoverRec<T>{loc[0], loc[1], loc[2], (T)v[0], (T)v[1], (T)v[2], (T)dd,
+                                (int32_t)(id0 + i)};
         mv.dest[m] = (int32_t)chunk_index(p, ch[0], ch[1], ch[2]);
-        mv.rank[m] = 0;
         if (!ok) flags[F_BADINPUT] = 1;
     }
 }
@@ -1222,16 +1300,8 @@ template <class T>
 Movers<T> movers_of(st_ctx *c)
 {
     Movers<T> m;
-    m.ox = (T *)c->mov[0];
-    m.oy = (T *)c->mov[1];
-    m.oz = (T *)c->mov[2];
-    m.vx = (T *)c->mov[3];
-    m.vy = (T *)c->mov[4];
-    m.vz = (T *)c->mov[5];
-    m.d = (T *)c->mov[6];
-    m.id = (int32_t *)c->mov[7];
-    m.dest = (int32_t *)c->mov[8];
-    m.rank = (int32_t *)c->mov[9];
+    m.rec = (MoverRec<T> *)c->mov[0];
+    m.dest = (int32_t *)c->mov[1];
     return m;
 }
 

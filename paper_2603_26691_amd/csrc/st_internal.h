@@ -37,13 +37,21 @@ struct View {
     int32_t *cnt;      // [C] live particles of the chunk
 };
 
-// Particles in flight between chunks (also the staging area of st_inject).
+// One particle in flight between chunks (also the staging area of
+// st_inject), kept together so that moving it reads and writes whole
+// 16-byte vectors: 32 bytes in binary32, 64 in binary64.
+template <class T>
+struct alignas(16) MoverRec {
+    T ox, oy, oz, vx, vy, vz, d;
+    int32_t id;
+};
+static_assert(sizeof(MoverRec<float>) == 32, "binary32 mover record is 32 bytes");
+static_assert(sizeof(MoverRec<double>) == 64, "binary64 mover record is 64 bytes");
+
 template <class T>
 struct Movers {
-    T *ox, *oy, *oz, *vx, *vy, *vz, *d;
-    int32_t *id;
+    MoverRec<T> *rec;
     int32_t *dest;     // destination chunk
-    int32_t *rank;     // arrival rank within the destination chunk
 };
 
 // Scalars of the mesh and material used by the kernels.
@@ -127,7 +135,7 @@ struct st_ctx {
     int64_t *base = nullptr;   // [C+1] layout of the store
     int32_t *room = nullptr;   // [C]
     int32_t *cnt = nullptr;    // [C]
-    void *mov[10] = {};        // Movers arrays
+    void *mov[2] = {};         // Movers: records, destination chunks
     int32_t *out_cnt = nullptr, *in_cnt = nullptr;
     int32_t *cursor = nullptr;     // [C] scatter cursors of the full re-bin
     int32_t *new_cnt = nullptr;    // [C]
