@@ -104,6 +104,9 @@ class Oracle:
             "or_run_rotating": (None, [M, _P, _P, _I64, _P, _P, _P, _D, _I32, _P]),
             "or_adjoint": (ctypes.c_int, [M, _P, _I64, _P, _P, _P, _D, _I32, _P, _P, _P]),
             "or_ec_estimate": (None, [_I64, _I32, _P, _P, _P, _P]),
+            "or_hilbert_index": (_I64, [_I32, _P]),
+            "or_hilbert_positions": (ctypes.c_int, [_I32, _I64, _I64, _I64, _I64, _P, _P, _P]),
+            "or_bounding_boxes": (None, [_I64, _P, _P, _I64, _I64, _I64, _P]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(lib, name)
@@ -191,6 +194,31 @@ class Oracle:
         self.lib.or_ec_estimate(S_last.size, int(kind), _ptr(S_last), _ptr(state["S_prev2"]),
                                 _ptr(state["ext_prev"]), _ptr(out))
         return out
+
+    def hilbert_index(self, order, xyz):
+        c = np.ascontiguousarray(xyz, dtype=np.int32).reshape(3)
+        return int(self.lib.or_hilbert_index(int(order), _ptr(c)))
+
+    def hilbert_positions(self, order, nseg, seg_begin, seg_end, per_seg, L, u):
+        """Positions [n, 3] of segments [seg_begin, seg_end), per_seg each."""
+        n = (seg_end - seg_begin) * per_seg
+        u = _f64(u, (n, 3))
+        Lc = _f64(L, (3,))
+        x = np.zeros((n, 3))
+        r = self.lib.or_hilbert_positions(int(order), int(nseg), int(seg_begin), int(seg_end),
+                                          int(per_seg), _ptr(Lc), _ptr(u), _ptr(x))
+        if r != 0:
+            raise ValueError("or_hilbert_positions rejected its arguments")
+        return x
+
+    def bounding_boxes(self, x, ids, id0, per_part, nparts):
+        """[nparts, 6] boxes (min xyz, max xyz) of the id partitions."""
+        x = _f64(x, (-1, 3))
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        box = np.zeros((nparts, 6))
+        self.lib.or_bounding_boxes(x.shape[0], _ptr(x), _ptr(ids), int(id0), int(per_part),
+                                   int(nparts), _ptr(box))
+        return box
 
     def adjoint(self, mesh, Uf, x0, up0, d, dt, nsteps, lam):
         """Returns (dL/dUf, dL/dd) for dL/dSu_int = lam."""

@@ -360,3 +360,92 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
     free(scratch);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Hilbert curve and segments (Sec. 2.2)                                     */
+/* ------------------------------------------------------------------------ */
+
+int64_t or_hilbert_index(int32_t order, const int32_t xyz[3])
+{
+    /* Skilling's axes-to-transpose: undo the rotations and reflections from
+     * the most significant bit down, then Gray-encode. */
+    uint32_t X[3] = {(uint32_t)xyz[0], (uint32_t)xyz[1], (uint32_t)xyz[2]};
+    const uint32_t M = 1u << (order - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;                       /* invert low bits of x */
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;   /* exchange with x */
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    /* interleave: bit b of the index, counted from the top, comes from axis
+     * (b mod 3) at bit level (order - 1 - b / 3) */
+    int64_t h = 0;
+    for (int level = order - 1; level >= 0; --level)
+        for (int i = 0; i < 3; ++i) h = (h << 1) | (int64_t)((X[i] >> level) & 1u);
+    return h;
+}
+
+int or_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_begin, int64_t seg_end,
+                         int64_t per_seg, const double L[3], const double *u, double *x)
+{
+    if (order < 1 || order > 10 || nseg < 1 || per_seg < 1 || seg_begin < 0 ||
+        seg_end > nseg || seg_begin > seg_end)
+        return -1;
+    const int64_t side = (int64_t)1 << order;
+    const int64_t V = side * side * side;
+    if (nseg > V) return -1;
+    /* table: curve position -> voxel, by inverting the index over the lattice */
+    int32_t *vox = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)V);
+    if (!vox) return -1;
+    for (int32_t k = 0; k < side; ++k)
+        for (int32_t j = 0; j < side; ++j)
+            for (int32_t i = 0; i < side; ++i) {
+                const int32_t c[3] = {i, j, k};
+                const int64_t h = or_hilbert_index(order, c);
+                vox[3 * h] = i;
+                vox[3 * h + 1] = j;
+                vox[3 * h + 2] = k;
+            }
+    int64_t n = 0;
+    for (int64_t sg = seg_begin; sg < seg_end; ++sg) {
+        const int64_t v0 = sg * V / nseg, v1 = (sg + 1) * V / nseg;
+        const int64_t nv = v1 - v0;
+        for (int64_t k = 0; k < per_seg; ++k, ++n) {
+            const int64_t v = v0 + k * nv / per_seg;
+            for (int a = 0; a < 3; ++a)
+                x[3 * n + a] = ((double)vox[3 * v + a] + u[3 * n + a]) * (L[a] / (double)side);
+        }
+    }
+    free(vox);
+    return 0;
+}
+
+void or_bounding_boxes(int64_t np, const double *x, const int64_t *id, int64_t id0,
+                       int64_t per_part, int64_t nparts, double *box)
+{
+    for (int64_t p = 0; p < nparts; ++p)
+        for (int a = 0; a < 3; ++a) {
+            box[6 * p + a] = INFINITY;
+            box[6 * p + 3 + a] = -INFINITY;
+        }
+    for (int64_t q = 0; q < np; ++q) {
+        if (id[q] < id0) continue;
+        const int64_t p = (id[q] - id0) / per_part;
+        if (p >= nparts) continue;
+        for (int a = 0; a < 3; ++a) {
+            if (x[3 * q + a] < box[6 * p + a]) box[6 * p + a] = x[3 * q + a];
+            if (x[3 * q + a] > box[6 * p + 3 + a]) box[6 * p + 3 + a] = x[3 * q + a];
+        }
+    }
+}

@@ -117,6 +117,34 @@ void or_run_rotating(const or_mesh *m, const double *U0, const double *cs,
 void or_ec_estimate(int64_t n, int32_t kind, const double *S_last, double *S_prev2,
                     double *ext_prev, double *applied);
 
+/* Hilbert index of voxel (x, y, z) on the 2^order lattice per axis
+ * (paper Sec. 2.2, particle initialisation along a Hilbert curve): the
+ * published transpose algorithm of Skilling (AIP Conf. Proc. 707, 2004),
+ * axes to transpose, then the transpose's bits interleaved most significant
+ * first (x before y before z).  order 1..10. */
+int64_t or_hilbert_index(int32_t order, const int32_t xyz[3]);
+
+/* Placement of particles by Hilbert segments (Sec. 2.2): the 8^order voxels in
+ * curve order are cut into nseg consecutive segments, segment s holding
+ * voxels [floor(s V / nseg), floor((s+1) V / nseg)), V = 8^order.  Particle k
+ * (0 <= k < per_seg) of segment s lies in the segment's voxel
+ * floor(k nv / per_seg) (nv voxels in the segment: counts per voxel differ by
+ * at most one and every segment holds exactly per_seg particles), at
+ * x_a = (c_a + u_a) (L_a / 2^order) with u in [0,1)^3 given.  Writes the
+ * positions of segments [seg_begin, seg_end) in order ([n][3],
+ * n = (seg_end - seg_begin) per_seg).  The voxel of a curve position is found
+ * by inverting or_hilbert_index over the whole lattice.  Returns 0, or -1 on
+ * bad arguments or when the table cannot be allocated. */
+int or_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_begin, int64_t seg_end,
+                         int64_t per_seg, const double L[3], const double *u, double *x);
+
+/* Axis-aligned bounding boxes of particle partitions: partition p holds the
+ * particles with id in [id0 + p per_part, id0 + (p+1) per_part); box p is
+ * (min x, min y, min z, max x, max y, max z) over them (Sec. 2.2, chunk
+ * bounding boxes).  An empty partition gets min = +inf, max = -inf. */
+void or_bounding_boxes(int64_t np, const double *x, const int64_t *id, int64_t id0,
+                       int64_t per_part, int64_t nparts, double *box);
+
 /* Reverse-mode derivative of nsteps single-sub-step calls of or_step
  * starting from (x0, up0), for a loss whose derivative with respect to the
  * time-integrated source Su_int is lambda ([3][n2][n1][n0]).  Adds dL/dUf to

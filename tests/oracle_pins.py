@@ -11,6 +11,10 @@ disagrees with something the paper or the mathematics fixes:
     first-order convergence to the analytic Stokes-drag solution
     (Sec. 2.5 states first order);
   * the textbook Stokes settling speed of a 20 um water droplet in air;
+  * the Hilbert curve's defining properties (bijection, face-neighbour
+    steps, octant self-similarity), segment placement (every particle in a
+    voxel of its segment, balanced voxel counts) and partition bounding
+    boxes by brute force (Sec. 2.2);
   * Schiller-Naumann drag (Sec. 2.1): the settling speed from the force
     balance with the drag coefficient C_D = 24/Re (1 + 0.15 Re^0.687), solved
     by bisection, and the measured fall speeds of 0.2 and 0.4 mm raindrops;
@@ -554,13 +558,99 @@ def pin_two_way_relaxation(orc):
     assert errs[-1] < 1e-5, f"two-way relaxation error {errs[-1]}"
 
 
+# ---------------------------------------------------------------------------
+# Hilbert segments and bounding boxes (paper Sec. 2.2)
+# ---------------------------------------------------------------------------
+def _hilbert_path(orc, order):
+    side = 1 << order
+    path = [None] * side ** 3
+    for k in range(side):
+        for j in range(side):
+            for i in range(side):
+                h = orc.hilbert_index(order, (i, j, k))
+                assert 0 <= h < side ** 3 and path[h] is None, "Hilbert index is a bijection"
+                path[h] = (i, j, k)
+    return path
+
+
+def pin_hilbert_curve(orc):
+    # A Hilbert curve visits every voxel once (bijection), moves to a face
+    # neighbour at every step, and is self-similar: each run of 8^(k-1)
+    # consecutive indices fills one octant, and the octants follow each
+    # other through shared faces.  This orientation starts at the origin and
+    # ends at the far corner along x.
+    for order in (1, 2, 3, 4):
+        side = 1 << order
+        path = _hilbert_path(orc, order)
+        for h in range(len(path) - 1):
+            dist = sum(abs(a - b) for a, b in zip(path[h], path[h + 1]))
+            assert dist == 1, f"order {order}: step {h} is not to a face neighbour"
+        assert path[0] == (0, 0, 0) and path[-1] == (side - 1, 0, 0)
+        if order >= 2:
+            sub = 8 ** (order - 1)
+            half = side // 2
+            octs = []
+            for m in range(8):
+                cells = path[m * sub:(m + 1) * sub]
+                o = {tuple(c // half for c in v) for v in cells}
+                assert len(o) == 1, f"order {order}: run {m} spans several octants"
+                octs.append(o.pop())
+            assert len(set(octs)) == 8
+            for m in range(7):
+                assert sum(abs(a - b) for a, b in zip(octs[m], octs[m + 1])) == 1
+
+
+def pin_hilbert_segments(orc):
+    rng = np.random.default_rng(41)
+    order, nseg, per_seg = 3, 37, 50          # 512 voxels: 13 or 14 per segment
+    L = np.array([0.5, 0.25, 1.0])            # dyadic: exact voxel arithmetic
+    side = 1 << order
+    hv = L / side
+    u = rng.random((nseg * per_seg, 3))
+    x = orc.hilbert_positions(order, nseg, 0, nseg, per_seg, L, u)
+    V = side ** 3
+    for s in range(nseg):
+        v0, v1 = s * V // nseg, (s + 1) * V // nseg
+        xs = x[s * per_seg:(s + 1) * per_seg]
+        c = np.floor(xs / hv).astype(int)
+        hs = [orc.hilbert_index(order, tuple(int(t) for t in cc)) for cc in c]
+        assert all(v0 <= h < v1 for h in hs), f"segment {s}: particle outside its voxels"
+        # reading: particles are laid along the curve, so their voxel index
+        # never decreases within a segment
+        assert all(hs[i] <= hs[i + 1] for i in range(len(hs) - 1)), \
+            f"segment {s}: particles not in curve order"
+        counts = np.bincount(np.array(hs) - v0, minlength=v1 - v0)
+        assert counts.sum() == per_seg and counts.max() - counts.min() <= 1, \
+            f"segment {s}: voxel counts {counts}"
+        # (c + u) rounds to the binary64 spacing at c < 8: 2^-50
+        assert np.abs(xs / hv - c - u[s * per_seg:(s + 1) * per_seg]).max() <= 2.0 ** -50, \
+            "the given uniforms place the particle inside its voxel"
+    # a slice of the segments gives the same particles as the full run
+    xp = orc.hilbert_positions(order, nseg, 5, 9, per_seg, L, u[5 * per_seg:9 * per_seg])
+    assert np.array_equal(xp, x[5 * per_seg:9 * per_seg])
+
+
+def pin_bounding_boxes(orc):
+    rng = np.random.default_rng(42)
+    x = rng.random((300, 3))
+    ids = rng.permutation(300).astype(np.int64) + 7
+    box = orc.bounding_boxes(x, ids, 7, 40, 9)   # partitions 0..7 full-ish, 8 empty
+    for p in range(9):
+        sel = (ids >= 7 + 40 * p) & (ids < 7 + 40 * (p + 1))
+        if sel.any():
+            want = np.concatenate([x[sel].min(axis=0), x[sel].max(axis=0)])
+            assert np.array_equal(box[p], want), f"box {p}"
+        else:
+            assert np.all(box[p, :3] == np.inf) and np.all(box[p, 3:] == -np.inf)
+
+
 ALL_PINS = [
     pin_cell_brute_force, pin_wrap, pin_interp_cell_centre, pin_interp_affine,
     pin_interp_shift, pin_interp_ngp, pin_interp_transpose, pin_closed_form_uniform,
     pin_terminal_velocity, pin_first_order, pin_conservation, pin_start_cell_deposit,
     pin_rotating_field, pin_adjoint_fd, pin_adjoint_fd_sn, pin_sn_terminal_velocity,
     pin_sn_force, pin_ec_conservative, pin_ec_exact_histories,
-    pin_two_way_relaxation,
+    pin_two_way_relaxation, pin_hilbert_curve, pin_hilbert_segments, pin_bounding_boxes,
 ]
 
 

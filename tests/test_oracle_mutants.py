@@ -110,6 +110,28 @@ MUTANTS = {
         ("double tausbar = taubar / f;", "double tausbar = taubar;"),
     "adjoint: Schiller-Naumann derivative exponent":
         ("pow(Re, 0.687 - 1.0)", "pow(Re, 0.687)"),
+    "Hilbert: invert and exchange swapped":
+        ("if (X[i] & Q) {\n                X[0] ^= P;", "if (!(X[i] & Q)) {\n                X[0] ^= P;"),
+    "Hilbert: Gray encoding from the wrong neighbour":
+        ("for (int i = 1; i < 3; ++i) X[i] ^= X[i - 1];", "for (int i = 1; i < 3; ++i) X[i - 1] ^= X[i];"),
+    "Hilbert: correction mask from x instead of z":
+        ("if (X[2] & Q) t ^= Q - 1;", "if (X[0] & Q) t ^= Q - 1;"),
+    "Hilbert: axes interleaved z first":
+        ("h = (h << 1) | (int64_t)((X[i] >> level) & 1u);", "h = (h << 1) | (int64_t)((X[2 - i] >> level) & 1u);"),
+    "Hilbert: undo loop stops one level early":
+        ("for (uint32_t Q = M; Q > 1; Q >>= 1) {\n        const uint32_t P = Q - 1;",
+         "for (uint32_t Q = M; Q > 2; Q >>= 1) {\n        const uint32_t P = Q - 1;"),
+    "segments: voxel of a particle by modulo":
+        ("const int64_t v = v0 + k * nv / per_seg;", "const int64_t v = v0 + k % nv;"),
+    "segments: start rounded up":
+        ("const int64_t v0 = sg * V / nseg, v1", "const int64_t v0 = (sg * V + nseg - 1) / nseg, v1"),
+    "segments: voxel width from side - 1":
+        ("* (L[a] / (double)side);", "* (L[a] / (double)(side - 1));"),
+    "bounding boxes: partition off by one":
+        ("const int64_t p = (id[q] - id0) / per_part;", "const int64_t p = (id[q] - id0 + 1) / per_part;"),
+    "bounding boxes: min and max swapped":
+        ("if (x[3 * q + a] < box[6 * p + a]) box[6 * p + a] = x[3 * q + a];",
+         "if (x[3 * q + a] > box[6 * p + a]) box[6 * p + a] = x[3 * q + a];"),
     "extrapolator-corrector: corrector sign":
         ("double correction = S_last[i] - ext_prev[i];", "double correction = S_last[i] + ext_prev[i];"),
     "extrapolator-corrector: linear coefficients swapped":
