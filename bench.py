@@ -1,7 +1,8 @@
 """Benchmark of the per-particle time step on one MI355X.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tg128] [--form fp32_local]
-                [--drag stokes] [--no-fp64] [--no-sn] [--no-adjoint] [--no-scale] [--no-cpu]
+                [--drag stokes] [--no-fp64] [--no-sn] [--no-hilbert] [--no-adjoint] [--no-scale]
+                [--no-cpu]
 
 A step is one pass of the whole hot path (gather, integrate, deposit,
 relocate and re-bin) over every particle of the workload.  Inputs are
@@ -10,8 +11,9 @@ steps are timed with events on the stream the kernels run on, bracketed by
 device synchronisations.  Prints one JSON line with the whole-job
 particle-steps/s, the step kernel's roofline figures, and beside them: the
 FP64 form on the same workload, the same run with Schiller-Naumann drag,
-forward+adjoint throughput (64^3, 1e6
-particles, checkpoints every 20 steps), the 1.4e9-particle 512^3 run with
+Hilbert-segment placement and partition bounding boxes, forward+adjoint
+throughput (64^3, 1e6 particles, checkpoints every 20 steps), the
+1.4e9-particle 512^3 run with
 the field update on a second stream, and the FP64 oracle timed on this
 host's cores on a bounded sample of the workload.
 """
@@ -153,6 +155,54 @@ def leg_adjoint(pkg, torch, np, synth):
             "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all())}
 
 
+def leg_hilbert(pkg, torch, np, w, reps=10):
+    """Hilbert-segment placement and partition bounding boxes on the workload's
+    particle count: the 2^k-per-axis voxel lattice of the mesh cut into 4096
+    segments (one per chunk of the mesh), uniforms drawn on the device."""
+    order = max(1, int(round(np.log2(w.n[0]))))
+    nseg = 4096
+    per_seg = w.P // nseg
+    n = nseg * per_seg
+    t = make_tracker(pkg, w, "fp32_local")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w.seed)
+    u = torch.rand((n, 3), dtype=torch.float64, device="cuda", generator=gen)
+    x = t.hilbert_positions(order, nseg, 0, nseg, per_seg, u)   # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        x = t.hilbert_positions(order, nseg, 0, nseg, per_seg, u)
+    e1.record()
+    torch.cuda.synchronize()
+    place_ms = e0.elapsed_time(e1) / reps
+    up = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+    d = torch.full((n,), 20e-6, dtype=torch.float64, device="cuda")
+    t.inject_hilbert(order, nseg, 0, nseg, per_seg, u, up, d)
+    del x, up, d, u
+    U = field_of(torch, np, w, "fp32_local")
+    t.step(U, w.dt)
+    box = t.bounding_boxes(0, per_seg, nseg)                      # warm-up
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        box = t.bounding_boxes(0, per_seg, nseg)
+    e1.record()
+    torch.cuda.synchronize()
+    box_ms = e0.elapsed_time(e1) / reps
+    vol = (box[:, 3:] - box[:, :3]).prod(dim=1).mean().item() / float(np.prod(w.L))
+    t.close()
+    torch.cuda.empty_cache()
+    return {"particles": n, "order": order, "segments": nseg,
+            "placement_ms": place_ms, "placement_particles_per_s": n / (place_ms / 1e3),
+            "placement_GBps": n * 48 / (place_ms / 1e3) / 1e9,
+            "placement_bytes": "48 B/particle (uniforms in, positions out)",
+            "bbox_ms": box_ms, "bbox_particles_per_s": n / (box_ms / 1e3),
+            "bbox_GBps": n * 16 / (box_ms / 1e3) / 1e9,
+            "bbox_bytes": "16 B/particle (offsets and id), after one step",
+            "mean_box_volume_fraction": vol}
+
+
 def leg_scale(pkg, torch, np, synth):
     """512^3, 1.4e9 particles (60 % in one plume), field rotated 1 degree per
     step on the second stream: throughput, overlap and the step kernel's
@@ -208,6 +258,8 @@ def main():
     ap.add_argument("--drag", default="stokes", choices=["stokes", "schiller_naumann"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form leg")
     ap.add_argument("--no-sn", action="store_true", help="skip the Schiller-Naumann leg")
+    ap.add_argument("--no-hilbert", action="store_true",
+                    help="skip the Hilbert placement and bounding-box leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1.4e9-particle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -277,6 +329,8 @@ def main():
             "value": w.P * steps / (rsn["ms"] / 1e3), "ms_per_step": rsn["ms"] / steps,
             "roofline": roofline(args.form, w, rsn["kernel_ms"], rsn["launches"],
                                  rsn["stats"]["items"], "schiller_naumann")}
+    if not args.no_hilbert:
+        out["hilbert"] = leg_hilbert(pkg, torch, np, w)
     if not args.no_adjoint:
         out["fwd_adjoint"] = leg_adjoint(pkg, torch, np, synth)
     if not args.no_scale:

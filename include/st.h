@@ -218,6 +218,41 @@ st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
 st_status st_timing(st_ctx *ctx, int32_t enable, double *kernel_ms,
                     int64_t *launches);
 
+/* Positions of new particles placed by Hilbert-curve segments (paper
+ * Sec. 2.2, initialisation).  The domain [0,L) is a lattice of 2^order voxels
+ * per axis (order 1..10) visited in Hilbert-curve order (the orientation of
+ * Skilling's transpose algorithm, AIP Conf. Proc. 707, 2004: the curve starts
+ * in voxel (0,0,0) and ends in (2^order - 1, 0, 0)); its V = 8^order voxels are
+ * cut into nseg (1..V) consecutive segments, segment s holding curve positions
+ * [floor(s V / nseg), floor((s+1) V / nseg)).  Particle k (0 <= k < per_seg)
+ * of segment s lies in the segment's voxel number floor(k nv / per_seg), nv its
+ * voxel count, at x_a = (c_a + u_a) L_a / 2^order, c the voxel and u[3] in
+ * [0,1) given by the caller.  Writes x ([n][3] binary64) for the particles of
+ * segments [seg_begin, seg_end) in order, n = (seg_end - seg_begin) per_seg
+ * (per_seg 1..2^31).  u and x: device memory when on_device, else host. */
+st_status st_hilbert_positions(st_ctx *ctx, int32_t order, int64_t nseg, int64_t seg_begin,
+                               int64_t seg_end, int64_t per_seg, const double *u, double *x,
+                               int32_t on_device, void *hip_stream);
+
+/* Injects the particles that st_hilbert_positions places, with velocities up
+ * ([n][3]) and diameters d ([n]); their ids continue the injection order, so
+ * particle k of segment s gets id first + (s - seg_begin) per_seg + k.  Any
+ * range of segments can be injected independently (the placement is global
+ * and deterministic).  Errors as st_inject; host u outside [0,1) is
+ * ST_ERR_INVALID. */
+st_status st_inject_hilbert(st_ctx *ctx, int32_t order, int64_t nseg, int64_t seg_begin,
+                            int64_t seg_end, int64_t per_seg, const double *u, const double *up,
+                            const double *d, int32_t on_device, void *hip_stream);
+
+/* Axis-aligned bounding boxes of particle partitions (paper Sec. 2.2, chunk
+ * bounding boxes): partition p (0 <= p < nparts) holds the particles with id in
+ * [id0 + p per_part, id0 + (p+1) per_part).  boxes ([nparts][6] binary64:
+ * min x, min y, min z, max x, max y, max z, over the positions st_get_particles
+ * returns; device memory when on_device) receives them; an empty partition gets
+ * min = +inf and max = -inf. */
+st_status st_bounding_boxes(st_ctx *ctx, int64_t id0, int64_t per_part, int64_t nparts,
+                            double *boxes, int32_t on_device, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

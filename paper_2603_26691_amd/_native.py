@@ -65,6 +65,9 @@ SIGNATURES = {
     "st_timing": (_I, [_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "st_ec_estimate": (_I, [_P, _I32, _P, _P, _I, _P]),
     "st_ec_reset": (_I, [_P, _P]),
+    "st_hilbert_positions": (_I, [_P, _I32, _I64, _I64, _I64, _I64, _P, _P, _I32, _P]),
+    "st_inject_hilbert": (_I, [_P, _I32, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P]),
+    "st_bounding_boxes": (_I, [_P, _I64, _I64, _I64, _P, _I32, _P]),
 }
 EXTRAPOLATORS = {"zero": 0, "const": 1, "linear": 2}
 

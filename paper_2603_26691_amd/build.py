@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscaletrack.so")
-SOURCES = ["st_api.cpp", "st_device.hip", "st_adjoint.hip"]
+SOURCES = ["st_api.cpp", "st_device.hip", "st_adjoint.hip", "st_hilbert.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

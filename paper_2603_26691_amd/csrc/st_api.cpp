@@ -605,3 +605,148 @@ st_status st_timing(st_ctx *c, int32_t enable, double *kernel_ms, int64_t *launc
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Hilbert-segment placement and partition bounding boxes
+// ---------------------------------------------------------------------------
+namespace {
+
+const char *hilbert_args_error(int32_t order, int64_t nseg, int64_t seg_begin, int64_t seg_end,
+                               int64_t per_seg)
+{
+    if (order < 1 || order > 10) return "order must be 1..10";
+    if (nseg < 1 || nseg > ((int64_t)1 << (3 * order))) return "nseg must be 1..8^order";
+    if (seg_begin < 0 || seg_end > nseg || seg_begin > seg_end)
+        return "need 0 <= seg_begin <= seg_end <= nseg";
+    if (per_seg < 1 || per_seg > ((int64_t)1 << 31)) return "per_seg must be 1..2^31";
+    return nullptr;
+}
+
+}  // namespace
+
+st_status st_hilbert_positions(st_ctx *c, int32_t order, int64_t nseg, int64_t seg_begin,
+                               int64_t seg_end, int64_t per_seg, const double *u, double *x,
+                               int on_device, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    try {
+        if (const char *m = hilbert_args_error(order, nseg, seg_begin, seg_end, per_seg))
+            return fail(c, ST_ERR_INVALID, std::string("st_hilbert_positions: ") + m);
+        const int64_t n = (seg_end - seg_begin) * per_seg;
+        if (n == 0) return ST_OK;
+        if (!u || !x) return fail(c, ST_ERR_INVALID, "st_hilbert_positions: null array");
+        ST_HIP(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        if (on_device) {
+            ST_HIP(st::launch_hilbert_positions(order, nseg, seg_begin, per_seg, c->prm.L, 0, n,
+                                                u, x, s));
+            return ST_OK;
+        }
+        double *tmp = nullptr;
+        if (hipMalloc((void **)&tmp, (size_t)n * 48) != hipSuccess)
+            return fail(c, ST_ERR_OOM, "st_hilbert_positions: temporaries");
+        hipError_t e = hipMemcpyAsync(tmp, u, (size_t)n * 24, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = st::launch_hilbert_positions(order, nseg, seg_begin, per_seg, c->prm.L, 0, n, tmp,
+                                             tmp + 3 * n, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(x, tmp + 3 * n, (size_t)n * 24, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return dev_fail(c, e, "st_hilbert_positions");
+        return ST_OK;
+    } catch (...) {
+        return fail(c, ST_ERR_OOM, "st_hilbert_positions: host allocation failed");
+    }
+}
+
+st_status st_inject_hilbert(st_ctx *c, int32_t order, int64_t nseg, int64_t seg_begin,
+                            int64_t seg_end, int64_t per_seg, const double *u, const double *up,
+                            const double *d, int on_device, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    try {
+        if (const char *m = hilbert_args_error(order, nseg, seg_begin, seg_end, per_seg))
+            return fail(c, ST_ERR_INVALID, std::string("st_inject_hilbert: ") + m);
+        const int64_t n = (seg_end - seg_begin) * per_seg;
+        if (n == 0) return ST_OK;
+        if (!u || !up || !d) return fail(c, ST_ERR_INVALID, "st_inject_hilbert: null array");
+        if (c->count + c->pending + n > c->cap)
+            return fail(c, ST_ERR_CAPACITY, "st_inject_hilbert: capacity exceeded");
+        if (!c->tape.empty()) return fail(c, ST_ERR_STATE, "st_inject_hilbert: a tape is recorded");
+        if (!on_device) {
+            for (int64_t i = 0; i < n; ++i) {
+                for (int a = 0; a < 3; ++a)
+                    if (!(u[3 * i + a] >= 0.0 && u[3 * i + a] < 1.0))
+                        return fail(c, ST_ERR_INVALID,
+                                    "st_inject_hilbert: u outside [0, 1) at " + std::to_string(i));
+                if (!finite3(up + 3 * i) || !isfinite(d[i]) || !(d[i] > 0))
+                    return fail(c, ST_ERR_INVALID, "st_inject_hilbert: non-finite value or d <= 0 at " +
+                                                       std::to_string(i));
+            }
+        }
+        ST_HIP(hipSetDevice(c->device));
+        hipStream_t s = (hipStream_t)hip_stream;
+        // positions (and, from the host, the other inputs) in device batches,
+        // each injected as device arrays
+        const int64_t batch = std::min<int64_t>(n, (int64_t)1 << 22);
+        double *tmp = nullptr;
+        const size_t per = on_device ? 24 : 24 + 24 + 24 + 8;
+        if (hipMalloc((void **)&tmp, (size_t)batch * per) != hipSuccess)
+            return fail(c, ST_ERR_OOM, "st_inject_hilbert: temporaries");
+        st_status r = ST_OK;
+        hipError_t e = hipSuccess;
+        for (int64_t done = 0; done < n && r == ST_OK && e == hipSuccess; done += batch) {
+            const int64_t k = std::min<int64_t>(batch, n - done);
+            double *xs = tmp;
+            const double *us = u + 3 * done, *vs = up + 3 * done, *ds = d + done;
+            if (!on_device) {
+                double *tu = tmp + 3 * batch, *tv = tu + 3 * batch, *td = tv + 3 * batch;
+                e = hipMemcpyAsync(tu, us, (size_t)k * 24, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(tv, vs, (size_t)k * 24, hipMemcpyHostToDevice, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(td, ds, (size_t)k * 8, hipMemcpyHostToDevice, s);
+                us = tu;
+                vs = tv;
+                ds = td;
+            }
+            if (e == hipSuccess)
+                e = st::launch_hilbert_positions(order, nseg, seg_begin, per_seg, c->prm.L, done, k,
+                                                 us, xs, s);
+            if (e == hipSuccess) r = st_inject(c, k, xs, vs, ds, 1, hip_stream);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        if (e != hipSuccess) return dev_fail(c, e, "st_inject_hilbert");
+        return r;
+    } catch (...) {
+        return fail(c, ST_ERR_OOM, "st_inject_hilbert: host allocation failed");
+    }
+}
+
+st_status st_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64_t nparts,
+                            double *boxes, int on_device, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    if (!boxes) return fail(c, ST_ERR_INVALID, "st_bounding_boxes: null array");
+    if (id0 < 0 || per_part < 1 || nparts < 1)
+        return fail(c, ST_ERR_INVALID, "st_bounding_boxes: need id0 >= 0, per_part >= 1, nparts >= 1");
+    ST_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    st_status r = ensure_flushed(c, s);
+    if (r != ST_OK) return r;
+    if (on_device) {
+        ST_HIP(st::launch_bounding_boxes(c, id0, per_part, nparts, boxes, s));
+        return ST_OK;
+    }
+    double *tmp = nullptr;
+    if (hipMalloc((void **)&tmp, (size_t)nparts * 48) != hipSuccess)
+        return fail(c, ST_ERR_OOM, "st_bounding_boxes: temporaries");
+    hipError_t e = st::launch_bounding_boxes(c, id0, per_part, nparts, tmp, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(boxes, tmp, (size_t)nparts * 48, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return dev_fail(c, e, "st_bounding_boxes");
+    return ST_OK;
+}

@@ -192,5 +192,10 @@ hipError_t launch_ec(st_ctx *c, int kind, const double *S_last, double *applied,
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 size_t snapshot_bytes(const st_ctx *c);
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s);
+hipError_t launch_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_begin,
+                                    int64_t per_seg, const double L[3], int64_t first, int64_t n,
+                                    const double *u, double *x, hipStream_t s);
+hipError_t launch_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64_t nparts,
+                                 double *box, hipStream_t s);
 
 }  // namespace st

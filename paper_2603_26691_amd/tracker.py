@@ -103,6 +103,53 @@ class Tracker:
             N.check(N.lib().st_inject(self.ctx, n, P(x.ctypes.data), P(up.ctypes.data),
                                       P(d.ctypes.data), 0, _stream()), self.ctx)
 
+    def hilbert_positions(self, order, nseg, seg_begin, seg_end, per_seg, u):
+        """Positions [n, 3] float64 of segments [seg_begin, seg_end) placed along
+        the Hilbert curve (include/st.h); u [n, 3] uniforms, torch (device) or numpy."""
+        # the library validates the arguments; the arrays only need to match
+        n = max((seg_end - seg_begin) * per_seg, 0)
+        if isinstance(u, torch.Tensor):
+            u = u.to(self.device, torch.float64).contiguous()
+            assert u.numel() == 3 * n
+            x = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+            N.check(N.lib().st_hilbert_positions(self.ctx, int(order), int(nseg), int(seg_begin),
+                                                 int(seg_end), int(per_seg), _dptr(u), _dptr(x), 1,
+                                                 _stream()), self.ctx)
+            return x
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.size == 3 * n
+        x = np.empty((n, 3))
+        P = ctypes.c_void_p
+        N.check(N.lib().st_hilbert_positions(self.ctx, int(order), int(nseg), int(seg_begin),
+                                             int(seg_end), int(per_seg), P(u.ctypes.data),
+                                             P(x.ctypes.data), 0, _stream()), self.ctx)
+        return x
+
+    def inject_hilbert(self, order, nseg, seg_begin, seg_end, per_seg, u, up, d):
+        """Adds the particles of segments [seg_begin, seg_end) placed along the
+        Hilbert curve; torch tensors on the device or numpy arrays."""
+        args = (int(order), int(nseg), int(seg_begin), int(seg_end), int(per_seg))
+        n = max((seg_end - seg_begin) * per_seg, 0)
+        if isinstance(u, torch.Tensor):
+            u, up, d = (t.to(self.device, torch.float64).contiguous() for t in (u, up, d))
+            assert u.numel() == 3 * n and up.numel() == 3 * n and d.numel() == n
+            N.check(N.lib().st_inject_hilbert(self.ctx, *args, _dptr(u), _dptr(up), _dptr(d), 1,
+                                              _stream()), self.ctx)
+        else:
+            u, up, d = (np.ascontiguousarray(a, dtype=np.float64) for a in (u, up, d))
+            assert u.size == 3 * n and up.size == 3 * n and d.size == n
+            P = ctypes.c_void_p
+            N.check(N.lib().st_inject_hilbert(self.ctx, *args, P(u.ctypes.data), P(up.ctypes.data),
+                                              P(d.ctypes.data), 0, _stream()), self.ctx)
+
+    def bounding_boxes(self, id0, per_part, nparts):
+        """[nparts, 6] float64 on the device: (min xyz, max xyz) of the particles
+        with id in [id0 + p per_part, id0 + (p+1) per_part)."""
+        out = torch.empty((nparts, 6), dtype=torch.float64, device=self.device)
+        N.check(N.lib().st_bounding_boxes(self.ctx, int(id0), int(per_part), int(nparts),
+                                          _dptr(out), 1, _stream()), self.ctx)
+        return out
+
     def count(self):
         v = ctypes.c_int64()
         N.check(N.lib().st_count(self.ctx, ctypes.byref(v)), self.ctx)
