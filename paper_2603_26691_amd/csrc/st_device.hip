@@ -351,7 +351,6 @@ struct StepArgs {
     int32_t *hole;
     int32_t *inbox;          // arrivals of chunk c at inbox[base[c] + rank]
     int32_t *flags;
-    int64_t grid;            // launched workgroups (for the XCD remap)
     int32_t deposit;         // 0: move and re-bin only (tape recompute)
     int32_t epoch;           // tag of this step in the device flags
     Params p;
@@ -378,13 +377,13 @@ __device__ __forceinline__ float sn_re_pow(float re2)
 }
 __device__ __forceinline__ double sn_re_pow(double re2) { return pow(re2, 0.3435); }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
-// XCD walks a contiguous range of work items (neighbouring chunks share
-// their halo cells through that XCD's L2).
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t grid)
+// Workgroups are dispatched round-robin over the 8 XCDs; remap workgroup ids
+// below n so that each XCD walks a contiguous range of the n work items
+// (neighbouring chunks share their halo cells through that XCD's L2).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
 {
     const int64_t nx = 8;
-    const int64_t per = grid / nx, rem = grid % nx;
+    const int64_t per = n / nx, rem = n % nx;
     const int64_t x = bid % nx, k = bid / nx;
     return x * per + (x < rem ? x : rem) + k;
 }
@@ -468,8 +467,11 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ int32_t dcount[28], doff[28], dbase[27], nb_room[27];
     __shared__ int64_t nb_base[27];
 
-    const int64_t item = xcd_remap(blockIdx.x, a.grid);
-    if (item >= *a.nitems) return;
+    // the grid is sized for the most items a layout can have; the remap runs
+    // over the items this step has, so every XCD gets its share of them
+    const int64_t nact = *a.nitems;
+    if ((int64_t)blockIdx.x >= nact) return;
+    const int64_t item = xcd_remap(blockIdx.x, nact);
     const View<T> &V = a.V;
     const int64_t c = a.items[2 * item];
     const int64_t seg = a.items[2 * item + 1];
@@ -1438,7 +1440,6 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         a.hole = c->hole;
         a.inbox = c->inbox;
         a.flags = c->flags;
-        a.grid = c->max_items;
         a.deposit = deposit;
         a.epoch = c->epoch;
         a.p = c->prm;
