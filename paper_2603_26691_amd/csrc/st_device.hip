@@ -377,15 +377,18 @@ __device__ __forceinline__ float sn_re_pow(float re2)
 }
 __device__ __forceinline__ double sn_re_pow(double re2) { return pow(re2, 0.3435); }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; remap workgroup ids
-// below n so that each XCD walks a contiguous range of the n work items
-// (neighbouring chunks share their halo cells through that XCD's L2).
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t n)
+// Workgroups are dispatched round-robin over the 8 XCDs.  Work items are
+// dealt to the XCDs in blocks of kXcdBlock consecutive items (neighbouring
+// chunks, which share halo cells through the XCD's L2), block j to XCD
+// j mod 8, so that every XCD gets a share of every region of the item list
+// and of its work, however uneven the chunk occupancy.  A bijection of
+// [0, R), R the item count rounded up to whole rounds of 8 blocks; ids that
+// map past the items exit.
+constexpr int64_t kXcdBlock = 64;
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid)
 {
-    const int64_t nx = 8;
-    const int64_t per = n / nx, rem = n % nx;
-    const int64_t x = bid % nx, k = bid / nx;
-    return x * per + (x < rem ? x : rem) + k;
+    const int64_t x = bid % 8, k = bid / 8;
+    return ((k / kXcdBlock) * 8 + x) * kXcdBlock + k % kXcdBlock;
 }
 
 // G consecutive values at a G*sizeof(T)-aligned address
@@ -467,11 +470,10 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ int32_t dcount[28], doff[28], dbase[27], nb_room[27];
     __shared__ int64_t nb_base[27];
 
-    // the grid is sized for the most items a layout can have; the remap runs
-    // over the items this step has, so every XCD gets its share of them
-    const int64_t nact = *a.nitems;
-    if ((int64_t)blockIdx.x >= nact) return;
-    const int64_t item = xcd_remap(blockIdx.x, nact);
+    // the grid covers the most items a layout can have, rounded up to whole
+    // rounds of the remap
+    const int64_t item = xcd_remap(blockIdx.x);
+    if (item >= *a.nitems) return;
     const View<T> &V = a.V;
     const int64_t c = a.items[2 * item];
     const int64_t seg = a.items[2 * item + 1];
@@ -1320,7 +1322,9 @@ hipError_t dispatch(st_ctx *c, F &&f)
 template <class T, class A, int E, int I, int D>
 hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(c->max_items), dim3(kBlock), 0, s, a);
+    const int64_t round = 8 * kXcdBlock;
+    const int64_t grid = (c->max_items + round - 1) / round * round;
+    hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
