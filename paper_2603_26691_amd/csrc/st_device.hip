@@ -901,6 +901,9 @@ __device__ void fill_big_chunk(const RebinArgs<T> &a, int64_t c, int32_t out, in
     const int32_t ncnt = cnt - out + in;
     int32_t *H = a.hole + base;
     const int32_t *box = a.inbox + base;
+    // every thread has read the old count before thread 0 stores the new
+    // one at the end (the waves of the block arrive here at different times)
+    __syncthreads();
     if (ncnt >= cnt) {
         for (int32_t r = tid; r < in; r += nt)
             place_mover(V, base + (r < out ? H[r] : cnt + (r - out)), a.mv, box[r]);
@@ -1374,9 +1377,8 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
 {
     const RebinArgs<T> a = rebin_args<T>(c, npend);
     const int64_t C = c->C;
-    int64_t g = (C + kFillBlock / 64 - 1) / (kFillBlock / 64);  // a wave per chunk
-    const int64_t gi = c->max_items;              // one block per item in the count
-    if (gi > g) g = gi;
+    // a wave per chunk for the fill; the count (rare) strides over the items
+    int64_t g = (C + kFillBlock / 64 - 1) / (kFillBlock / 64);
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(kFillBlock), 0, s, a);
     const int64_t total = c->count + npend;

@@ -114,6 +114,14 @@ def test_lockstep_plume_ragged(orc):
     _run_lockstep(orc, w, "fp32_local", nsteps=4)
 
 
+def test_lockstep_crowded_chunk_fills(orc):
+    # 64^3 mesh, 2e6 droplets in four tight plumes: after a few steps single
+    # chunks receive or lose more than 256 movers in one step and take the
+    # workgroup-wide fill, several of them per fill workgroup
+    w = workload("plume256", n=(64, 64, 64), P=2_000_000)
+    _run_lockstep(orc, w, "fp64", nsteps=9)
+
+
 def test_free_run_tg32_fp64(orc):
     """Config-0 workload in full (1e5 droplets, 100 steps of 1e-4 s), FP64 form."""
     w = workload("tg32")
