@@ -2,7 +2,7 @@
 //
 // One step of the particle method (paper Sec. 2.1 equations of motion and
 // momentum source, Sec. 2.5 interpolation, deposit and time integration)
-// is seven launches:
+// is six launches:
 //   step      one workgroup per work item (a run of at most kSeg particles of
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
@@ -12,12 +12,13 @@
 //             a workgroup's reservations (mover list, vacated slots, one
 //             arrival count per neighbouring chunk), and flush the
 //             accumulator with one read-modify-write (or one atomic, for
-//             chunks split over several items) per cell;
-//   check     the room check of every chunk (a mover files itself in its
-//             destination chunk's inbox when it is emitted);
-//   fill      one wave per chunk: arrivals and, when the chunk shrank, its
-//             tail particles fill the vacated slots, keeping the chunk dense
-//             (or, when a full re-bin is due, the re-keyed counts);
+//             chunks split over several items) per cell.  A mover files
+//             itself in its destination chunk's inbox; arrivals that do not
+//             fit the destination's free slots force the full re-bin;
+//   fill      one wave per chunk (a workgroup for a crowded one): arrivals
+//             and, when the chunk shrank, its tail particles fill the
+//             vacated slots, keeping the chunk dense (or, when a full re-bin
+//             is due, the re-keyed counts);
 //   rooms, scatter, commit
 //             only when a chunk ran out of room, the mover list overflowed
 //             or particles were injected: a full counting-sort re-bin into
@@ -438,9 +439,11 @@ __device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, i
         a.mv.rec[m] = MoverRec<T>{x, y, z, vx, vy, vz, dd, id};
         a.mv.dest[m] = (int32_t)cn;
         const int32_t r = atomicAdd(&a.in_cnt[cn], 1);
-        // an arrival rank beyond the room means the chunk overflows (the room
-        // check after the step sees it too); it is then never read
-        if (r < V.room[cn]) a.inbox[V.base[cn] + r] = (int32_t)m;
+        // arrivals must fit the destination's free slots (room - count, a
+        // bound that ignores its departures); one that does not forces the
+        // full re-bin, and its entry is never read
+        if (r < V.room[cn] - V.cnt[cn]) a.inbox[V.base[cn] + r] = (int32_t)m;
+        else a.flags[F_OVERFLOW] = a.epoch;
     } else {
         a.flags[F_OVERFLOW] = a.epoch;
     }
@@ -467,7 +470,7 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ A acc[3 * E3];
     __shared__ int32_t mstage[kMoverStage];
     __shared__ int32_t mcount, mbase_sh, hbase_sh;
-    __shared__ int32_t dcount[28], doff[28], dbase[27], nb_room[27];
+    __shared__ int32_t dcount[28], doff[28], dbase[27], nb_free[27];
     __shared__ int64_t nb_base[27];
 
     // the grid covers the most items a layout can have, rounded up to whole
@@ -753,7 +756,11 @@ __global__ void __launch_bounds__(kBlock)
             if (nb) {
                 dbase[lane] = r;
                 nb_base[lane] = V.base[dc];
-                nb_room[lane] = V.room[dc];
+                const int32_t fr = V.room[dc] - V.cnt[dc];
+                nb_free[lane] = fr;
+                // arrivals must fit the destination's free slots (a bound
+                // that ignores its departures), else the full re-bin runs
+                if (r + n > fr) a.flags[F_OVERFLOW] = a.epoch;
             }
             if (lane == 32) mbase_sh = r;
             if (lane == 33) hbase_sh = r;
@@ -793,20 +800,21 @@ __global__ void __launch_bounds__(kBlock)
         int64_t dest;
         int32_t r;
         int64_t dbas;
-        int32_t droom;
+        int32_t dfree;
         if (dir < 27) {   // within the direction's reservation
             dest = chunk_index(p, wrapi(cx + dir % 3 - 1, p.nc[0]),
                                wrapi(cy + (dir / 3) % 3 - 1, p.nc[1]),
                                wrapi(cz + dir / 9 - 1, p.nc[2]));
             r = dbase[dir] + rank;
             dbas = nb_base[dir];
-            droom = nb_room[dir];
+            dfree = nb_free[dir];
         } else {          // farther than one chunk: a reservation of its own
             dest = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
                                wrapi(cz + kz, p.nc[2]));
             r = atomicAdd(&a.in_cnt[dest], 1);
             dbas = V.base[dest];
-            droom = V.room[dest];
+            dfree = V.room[dest] - V.cnt[dest];
+            if (r >= dfree) a.flags[F_OVERFLOW] = a.epoch;
         }
         V.id[s0 + off] = -1 - mid[u];
         a.hole[base + hbase_sh + j] = (int32_t)(s0 + off - base);
@@ -814,27 +822,15 @@ __global__ void __launch_bounds__(kBlock)
             a.mv.rec[m] = MoverRec<T>{mx[u], my[u], mz[u], mvx[u], mvy[u], mvz[u], md[u],
                                       mid[u]};
             a.mv.dest[m] = (int32_t)dest;
-            // a rank beyond the room means the chunk overflows (the room
-            // check sees it too); the entry is then never read
-            if (r < droom) a.inbox[dbas + r] = (int32_t)m;
+            // a rank beyond the free slots has forced the full re-bin; its
+            // entry is never read
+            if (r < dfree) a.inbox[dbas + r] = (int32_t)m;
         } else {
             a.flags[F_OVERFLOW] = a.epoch;
         }
     }
 }
 
-// room check after the step: a chunk whose new count exceeds its room
-// forces the full re-bin
-template <class T>
-__global__ void k_check(View<T> V, int64_t C, const int32_t *out_cnt, const int32_t *in_cnt,
-                        int32_t *flags, int32_t epoch)
-{
-    bool bad = false;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
-         c += (int64_t)gridDim.x * blockDim.x)
-        bad |= (int64_t)V.cnt[c] - out_cnt[c] + in_cnt[c] > V.room[c];
-    if (__ballot(bad) != 0 && __lane_id() == 0) flags[F_OVERFLOW] = epoch;
-}
 
 // ---------------------------------------------------------------------------
 // re-bin after the step: the mover-only fill or the full counting sort
@@ -1478,10 +1474,6 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         if (r == hipSuccess && c->timing) r = hipEventRecord(ev[1], s);
         if (r != hipSuccess) return r;
 
-        hipLaunchKernelGGL((k_check<T>), dim3(grid_for(c->C, 1024)), dim3(256), 0, s, a.V, c->C,
-                           c->out_cnt, c->in_cnt, c->flags, c->epoch);
-        r = hipGetLastError();
-        if (r != hipSuccess) return r;
         return launch_rebin<T>(c, 0, s);
     });
 }
