@@ -2,7 +2,7 @@
 //
 // One step of the particle method (paper Sec. 2.1 equations of motion and
 // momentum source, Sec. 2.5 interpolation, deposit and time integration)
-// is six launches:
+// is five launches:
 //   step      one workgroup per work item (a run of at most kSeg particles of
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
@@ -19,11 +19,14 @@
 //             and, when the chunk shrank, its tail particles fill the
 //             vacated slots, keeping the chunk dense (or, when a full re-bin
 //             is due, the re-keyed counts);
-//   rooms, scatter, commit
+//   layout    work items of the next step from the counts, the reset of the
+//             counters, and, when a full re-bin is due, the rooms and bases
+//             of its layout (one workgroup);
+//   scatter, commit
 //             only when a chunk ran out of room, the mover list overflowed
 //             or particles were injected: a full counting-sort re-bin into
-//             the second store, copied back (decided on the device);
-//   items     work items of the next step, and the reset of the counters.
+//             the second store, copied back (decided on the device).
+// (Meshes of more than kScan1Max chunks scan with several launches.)
 // Device flags that decide between the two re-bins hold the tag (epoch) of
 // the step that raised them, so nothing has to clear them between steps.
 #include "st_internal.h"
@@ -304,8 +307,6 @@ __device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
     }
     a.out_cnt[c] = 0;
     a.in_cnt[c] = 0;
-    a.new_cnt[c] = 0;
-    a.cursor[c] = 0;
 }
 
 __device__ __forceinline__ void finish_flags(const ItemArgs &a)
@@ -330,6 +331,27 @@ __global__ void k_items(ItemArgs a)
          c += (int64_t)gridDim.x * blockDim.x)
         write_items(a, c);
     if (blockIdx.x == 0 && threadIdx.x == 0) finish_flags(a);
+}
+
+// one workgroup, after the fill or the re-keyed count (C <= kScan1Max).  After
+// a fill: the work items of the next step and the reset of the counters.
+// When a full re-bin is due: the rooms and bases of its layout and the item
+// offsets from the re-keyed counts; the scatter still walks the current
+// items, so the commit writes the new ones.
+__global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, Segments now,
+                                                  Segments rekeyed, ItemArgs a,
+                                                  const int32_t *flags)
+{
+    if (full_rebin(flags, a.epoch)) {
+        block_scan_all<int64_t>(rooms, a.C, nbase);
+        __syncthreads();
+        block_scan_all<int32_t>(rekeyed, a.C, a.noff);
+        return;
+    }
+    block_scan_all<int32_t>(now, a.C, a.noff);
+    __syncthreads();
+    for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x) write_items(a, c);
+    if (threadIdx.x == 0) finish_flags(a);
 }
 
 __global__ void k_set_flag(int32_t *flags, int which, int32_t v) { flags[which] = v; }
@@ -1073,7 +1095,7 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(RebinArgs<T> a)
 
 // Full re-bin, last pass: the second store and the new layout become the store.
 template <class T>
-__global__ void k_rekey_commit(RebinArgs<T> a)
+__global__ void k_rekey_commit(RebinArgs<T> a, ItemArgs ia, int items_here)
 {
     if (!full_rebin(a.flags, a.epoch)) return;
     const View<T> &V = a.V;
@@ -1094,7 +1116,11 @@ __global__ void k_rekey_commit(RebinArgs<T> a)
         V.cnt[c] = a.new_cnt[c];
         V.base[c] = a.nbase[c];
         V.room[c] = a.nroom[c];
+        a.new_cnt[c] = 0;   // ready for the next full re-bin
+        a.cursor[c] = 0;
+        if (items_here) write_items(ia, c);
     }
+    if (items_here && g0 == 0) finish_flags(ia);
     if (g0 == 0) a.flags[F_REPACKS] += 1;
 }
 
@@ -1380,11 +1406,23 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
     const int64_t total = c->count + npend;
     Rooms rooms{c->new_cnt, c->slots - total - (int64_t)kAlign * C,
                 total + (int64_t)kSlackMin * C, c->nroom};
+    const int64_t gs = c->max_items < 65536 ? c->max_items : 65536;
+    ItemArgs ia{C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
+                c->epoch};
+    if (C <= kScan1Max) {
+        // rooms (when due) and the next items in one workgroup
+        hipLaunchKernelGGL(k_layout1, dim3(1), dim3(1024), 0, s, rooms, c->nbase,
+                           Segments{c->cnt}, Segments{c->new_cnt}, ia, c->flags);
+        hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s,
+                           a, ia, 1);
+        return hipGetLastError();
+    }
     hipError_t e = scan<int64_t>(rooms, C, c->nbase, c->scan_tmp, c->flags, G_FULL, c->epoch, s);
     if (e != hipSuccess) return e;
-    const int64_t gs = c->max_items < 65536 ? c->max_items : 65536;
     hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, a,
+                       ia, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_items(c, s);
@@ -1417,6 +1455,8 @@ hipError_t launch_init(st_ctx *c, hipStream_t s)
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(c->C + 1)), dim3(256), 0, s, c->base, c->C + 1,
                        (int64_t)0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, c->flags, (int64_t)F_COUNT, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->new_cnt, c->C, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->cursor, c->C, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_items(c, s);
