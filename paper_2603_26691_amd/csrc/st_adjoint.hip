@@ -47,21 +47,27 @@ struct AdjArgs {
     int64_t grid;
     const T *u;              // field of the step [3][n2][n1][n0]
     const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
-    double *xb, *ub, *db;    // adjoint state by id ([P][3], [P][3], [P])
+    double *adj;             // adjoint state by id, [P][8]: xbar[3], ubar[3], dbar, unused
     double *Ubar;            // dL/du [3][n2][n1][n0]
     int64_t count;
     Params p;
     double dt;
 };
 
+// One workgroup of 256 threads per work item (wider workgroups, and more
+// workgroups over shorter runs, measured slower).
+constexpr int kAdjBlock = 256;
+
 template <class T, int E, int INTERP>
-__global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
+__global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
 {
     constexpr int S = E + 2;
     constexpr int S3 = S * S * S;
     constexpr int E3 = E * E * E;
     __shared__ T tile[3 * S3];
-    __shared__ double ubt[3 * S3];   // Ubar over the tile
+    // Ubar over the tile, summed in the state precision: a cell takes a few
+    // dozen terms per step, and every step's sum goes to binary64 globally
+    __shared__ T ubt[3 * S3];
 
     const int64_t item = blockIdx.x;
     if (item >= *a.nitems) return;
@@ -86,17 +92,33 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
         gz -= gz >= p.n[2] ? p.n[2] : 0;
         return ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx;
     };
-    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
-        const int comp = t / S3;
-        tile[t] = a.u[comp * ncell + tile_cell(t - comp * S3)];
-        ubt[t] = 0.0;
+    // the tile's loads are all issued before the first is used
+    {
+        constexpr int NT = (3 * S3 + kAdjBlock - 1) / kAdjBlock;
+        T vals[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int t = threadIdx.x + u * kAdjBlock;
+            if (t < 3 * S3) {
+                const int comp = t / S3;
+                vals[u] = a.u[comp * ncell + tile_cell(t - comp * S3)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int t = threadIdx.x + u * kAdjBlock;
+            if (t < 3 * S3) {
+                tile[t] = vals[u];
+                ubt[t] = T(0);
+            }
+        }
     }
     __syncthreads();
 
     const double dt = a.dt;
     const double inv_V = p.inv_V;
     const double *lam = a.lamC + c * 3 * E3;
-    for (int64_t q = s0 + threadIdx.x; q < s1; q += kBlock) {
+    for (int64_t q = s0 + threadIdx.x; q < s1; q += kAdjBlock) {
         const int64_t id = a.id[q];
         if (id < 0 || id >= a.count) continue;  // never in a saved store
         const double xi[3] = {(double)a.ox[q], (double)a.oy[q], (double)a.oz[q]};
@@ -156,9 +178,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
         const int cell = (cl[2] * E + cl[1]) * E + cl[0];
         double xb[3], ub[3], ufb[3];
         double mbar = 0.0, taubar = 0.0;
+        double *rec = a.adj + 8 * id;   // one 64-byte record per particle
         for (int ax = 0; ax < 3; ++ax) {
-            xb[ax] = a.xb[3 * id + ax];
-            ub[ax] = a.ub[3 * id + ax];
+            xb[ax] = rec[ax];
+            ub[ax] = rec[3 + ax];
         }
         for (int ax = 0; ax < 3; ++ax) {
             const double Jbar = -lam[ax * E3 + cell] * inv_V;
@@ -180,7 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
         for (int k = 0; k < nk; ++k) {
             double dot = 0.0;
             for (int comp = 0; comp < 3; ++comp) {
-                atomicAdd(&ubt[comp * S3 + tc[k]], w[k] * ufb[comp]);
+                atomicAdd(&ubt[comp * S3 + tc[k]], (T)(w[k] * ufb[comp]));
                 dot += (double)tile[comp * S3 + tc[k]] * ufb[comp];
             }
             if (INTERP == 0) {
@@ -191,14 +214,14 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(AdjArgs<T> a)
             }
         }
         for (int ax = 0; ax < 3; ++ax) {
-            a.xb[3 * id + ax] = xb[ax];
-            a.ub[3 * id + ax] = ub[ax];
+            rec[ax] = xb[ax];
+            rec[3 + ax] = ub[ax];
         }
-        a.db[id] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
+        rec[6] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < 3 * S3; t += kBlock) {
-        const double v = ubt[t];
+    for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) {
+        const double v = (double)ubt[t];
         if (v != 0.0) {
             const int comp = t / S3;
             atomicAdd(a.Ubar + comp * ncell + tile_cell(t - comp * S3), v);
@@ -230,6 +253,14 @@ __global__ void k_zero_f64(double *p, int64_t n)
         p[i] = 0.0;
 }
 
+// dL/dd of every particle out of the adjoint records
+__global__ void k_take_dbar(const double *adj, int64_t P, double *dd)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dd[i] = adj[8 * i + 6];
+}
+
 inline int64_t grid_of(int64_t n)
 {
     const int64_t g = (n + 255) / 256;
@@ -238,7 +269,7 @@ inline int64_t grid_of(int64_t n)
 
 template <class T>
 AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
-                    double *xb, double *ub, double *db, double *Ubar)
+                    double *adj, double *Ubar)
 {
     const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
     const T *st = reinterpret_cast<const T *>(snap + L.state);
@@ -258,9 +289,7 @@ AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const doubl
     a.grid = c->max_items;
     a.u = reinterpret_cast<const T *>(ts.u);
     a.lamC = lamC;
-    a.xb = xb;
-    a.ub = ub;
-    a.db = db;
+    a.adj = adj;
     a.Ubar = Ubar;
     a.count = c->count;
     a.p = c->prm;
@@ -271,7 +300,7 @@ AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const doubl
 template <class T>
 hipError_t launch_adjoint_step(st_ctx *c, const AdjArgs<T> &a, hipStream_t s)
 {
-    const dim3 g(c->max_items), b(kBlock);
+    const dim3 g(c->max_items), b(kAdjBlock);
     const bool ngp = c->prm.interp == 1;
     switch (c->prm.E) {
     case 2:
@@ -312,13 +341,11 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     const int64_t E3 = (int64_t)c->prm.E * c->prm.E * c->prm.E;
     const size_t sbytes = snapshot_bytes(c);
 
-    DevBuf final_state, lamC, xb, ub, db;
+    DevBuf final_state, lamC, adj;
     std::vector<DevBuf> steps((size_t)K);
     hipError_t e = final_state.alloc(sbytes);
     if (e == hipSuccess) e = lamC.alloc((size_t)c->C * 3 * E3 * 8);
-    if (e == hipSuccess) e = xb.alloc((size_t)P * 24);
-    if (e == hipSuccess) e = ub.alloc((size_t)P * 24);
-    if (e == hipSuccess) e = db.alloc((size_t)P * 8);
+    if (e == hipSuccess) e = adj.alloc((size_t)P * 64);
     for (int64_t k = 0; k < K && e == hipSuccess; ++k) e = steps[(size_t)k].alloc(sbytes);
     if (e != hipSuccess) return e;
 
@@ -333,9 +360,7 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
                        (double *)lamC.p);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * P)), dim3(256), 0, s, (double *)xb.p, 3 * P);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * P)), dim3(256), 0, s, (double *)ub.p, 3 * P);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(P)), dim3(256), 0, s, (double *)db.p, P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, (double *)adj.p, 8 * P);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
 
@@ -356,15 +381,16 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
             if (c->form == ST_FORM_FP64)
                 e = launch_adjoint_step<double>(
                     c, adj_args<double>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
-                                        (double *)xb.p, (double *)ub.p, (double *)db.p, dU), s);
+                                        (double *)adj.p, dU), s);
             else
                 e = launch_adjoint_step<float>(
                     c, adj_args<float>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
-                                       (double *)xb.p, (double *)ub.p, (double *)db.p, dU), s);
+                                       (double *)adj.p, dU), s);
             if (e != hipSuccess) return fail(e);
         }
     }
-    e = hipMemcpyAsync(dd, db.p, (size_t)P * 8, hipMemcpyDeviceToDevice, s);
+    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)adj.p, P, dd);
+    e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
     e = launch_snapshot(c, final_state.p, 1, s);
     if (e != hipSuccess) return fail(e);

@@ -172,7 +172,9 @@ def test_autograd_function():
     # a fresh binary32 copy of the field; the tracker keeps it alive while taped
     t2, _, S2 = _forward(w, "fp32_local", x, up, d, U.detach().float().contiguous(), K=3)
     gU, gd = (g.cpu().numpy() for g in t2.backward((2.0 * (S2 - T)).contiguous()))
-    assert _rel(U.grad.cpu().numpy(), gU) < 1e-12
+    # the same run twice: the binary32 tile sums of dL/du depend on the order
+    # of their atomic adds, so the two agree to binary32 rounding
+    assert _rel(U.grad.cpu().numpy(), gU) < 1e-6
     assert _rel(dd.grad.cpu().numpy(), gd) < 1e-12
     run.tracker.close()
     t2.close()
