@@ -51,7 +51,7 @@ void free_all(st_ctx *c)
     for (int k = 0; k < 2; ++k) (void)hipFree(c->mov[k]);
     void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->cursor,
                        c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
-                       c->scan_tmp, c->flags, c->src, c->stage64, c->fieldbuf[0],
+                       c->scan_tmp, c->room_denom, c->flags, c->src, c->stage64, c->fieldbuf[0],
                        c->fieldbuf[1], c->ec_prev, c->ec_ext};
     for (void *p : singles) (void)hipFree(p);
     for (auto &sn : c->snaps) (void)hipFree(sn.buf);
@@ -185,6 +185,7 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     A(&c->items, (size_t)c->max_items * 8);
     A(&c->nseg, (size_t)(C + 1) * 4);
     A(&c->scan_tmp, (size_t)(C / 1024 + 4) * 8);
+    A(&c->room_denom, 8);
     A(&c->flags, (size_t)st::F_COUNT * 4);
     A(&c->src, (size_t)3 * ncell * c->asize);
     if (ok != hipSuccess)

@@ -233,22 +233,70 @@ struct Segments {
     __device__ int32_t operator()(int64_t i) const { return (cnt[i] + kSeg - 1) / kSeg; }
 };
 
+// Share of the spare slots a chunk asks for in a re-binned layout: the
+// largest count among the chunk and its six face neighbours (periodic), plus
+// kSlackMin.  What a chunk can gain before the next re-bin is bounded by what
+// its neighbours can send, so a sparse chunk at the edge of a dense region
+// gets room for the arrivals from the dense side.
+struct RoomWeight {
+    const int32_t *cnt;
+    int32_t nc[3];
+    __device__ int64_t operator()(int64_t i) const
+    {
+        const int64_t x = i % nc[0], y = (i / nc[0]) % nc[1], z = i / ((int64_t)nc[0] * nc[1]);
+        const int64_t sx = 1, sy = nc[0], sz = (int64_t)nc[0] * nc[1];
+        const int64_t nb[6] = {
+            i + (x == nc[0] - 1 ? -(nc[0] - 1) * sx : sx), i + (x == 0 ? (nc[0] - 1) * sx : -sx),
+            i + (y == nc[1] - 1 ? -(nc[1] - 1) * sy : sy), i + (y == 0 ? (nc[1] - 1) * sy : -sy),
+            i + (z == nc[2] - 1 ? -(nc[2] - 1) * sz : sz), i + (z == 0 ? (nc[2] - 1) * sz : -sz)};
+        int32_t m = cnt[i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) m = max(m, cnt[nb[k]]);
+        return (int64_t)m + kSlackMin;
+    }
+};
+
 // rooms of a re-binned layout: the spare slots are shared out in proportion
-// to (count + kSlackMin), rounded down to whole groups of kAlign slots, on
-// top of the count rounded up to kAlign; also records the room
+// to the chunks' weights (denom = their sum), rounded down to whole groups of
+// kAlign slots, on top of the count rounded up to kAlign; also records the
+// room
 struct Rooms {
-    const int32_t *new_cnt;
+    RoomWeight w;
     int64_t spare, denom;
     int32_t *nroom;
     __device__ int64_t operator()(int64_t i) const
     {
-        const int64_t n = new_cnt[i];
-        const int64_t extra = denom > 0 ? spare * (n + kSlackMin) / denom : 0;
+        const int64_t n = w.cnt[i];
+        const int64_t extra = denom > 0 ? spare * w(i) / denom : 0;
         const int64_t r = (n + kAlign - 1) / kAlign * kAlign + extra / kAlign * kAlign;
         nroom[i] = (int32_t)r;
         return r;
     }
 };
+
+// the same, with the sum of the weights read from device memory (several
+// workgroups; written by k_room_denom)
+struct RoomsDev {
+    Rooms r;
+    const int64_t *denom;
+    __device__ int64_t operator()(int64_t i) const
+    {
+        Rooms q = r;
+        q.denom = *denom;
+        return q(i);
+    }
+};
+
+// sum of f(i), i < n, over one workgroup of 1024 threads (every thread gets it)
+template <class F>
+__device__ int64_t block_sum_all(const F &f, int64_t n)
+{
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += f(i);
+    int64_t tot;
+    block_excl_scan<int64_t>(s, tot);
+    return tot;
+}
 
 // ---------------------------------------------------------------------------
 // chunks and re-basing of chunk-local offsets
@@ -343,6 +391,7 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
                                                   const int32_t *flags)
 {
     if (full_rebin(flags, a.epoch)) {
+        rooms.denom = block_sum_all(rooms.w, a.C);
         block_scan_all<int64_t>(rooms, a.C, nbase);
         __syncthreads();
         block_scan_all<int32_t>(rekeyed, a.C, a.noff);
@@ -355,6 +404,23 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
 }
 
 __global__ void k_set_flag(int32_t *flags, int which, int32_t v) { flags[which] = v; }
+
+// when a full re-bin is due on a mesh of more than kScan1Max chunks: the sum
+// of the chunks' room weights, kScanBlock chunks per workgroup
+__global__ void __launch_bounds__(256) k_room_denom(RoomWeight w, int64_t C, int64_t *denom,
+                                                    const int32_t *flags, int32_t epoch)
+{
+    if (!full_rebin(flags, epoch)) return;
+    const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    int64_t s = 0;
+    for (int k = 0; k < kScanBlock / 256; ++k) {
+        const int64_t i = b0 + k * 256 + threadIdx.x;
+        if (i < C) s += w(i);
+    }
+    int64_t tot;
+    block_excl_scan<int64_t>(s, tot);
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)denom, (unsigned long long)tot);
+}
 
 // ---------------------------------------------------------------------------
 // the step kernel
@@ -899,6 +965,7 @@ struct RebinArgs {
     int32_t *new_cnt, *cursor;
     const int64_t *nbase;
     const int32_t *nroom;
+    int64_t *room_denom;     // sum of the room weights (zeroed by the count)
     int64_t slots;
     int32_t *flags;
     int32_t epoch;
@@ -1018,6 +1085,7 @@ template <class T>
 __device__ void rekey_count(const RebinArgs<T> &a)
 {
     const View<T> &V = a.V;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.room_denom = 0;
     const int64_t ni = *a.nitems;
     for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
         const int64_t c = a.items[2 * it], seg = a.items[2 * it + 1];
@@ -1387,6 +1455,7 @@ RebinArgs<T> rebin_args(st_ctx *c, int64_t npend)
     a.cursor = c->cursor;
     a.nbase = c->nbase;
     a.nroom = c->nroom;
+    a.room_denom = c->room_denom;
     a.slots = c->slots;
     a.flags = c->flags;
     a.epoch = c->epoch;
@@ -1404,8 +1473,8 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
     if (g > 65536) g = 65536;
     hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(kFillBlock), 0, s, a);
     const int64_t total = c->count + npend;
-    Rooms rooms{c->new_cnt, c->slots - total - (int64_t)kAlign * C,
-                total + (int64_t)kSlackMin * C, c->nroom};
+    const RoomWeight rw{c->new_cnt, {c->prm.nc[0], c->prm.nc[1], c->prm.nc[2]}};
+    const Rooms rooms{rw, c->slots - total - (int64_t)kAlign * C, 0, c->nroom};
     const int64_t gs = c->max_items < 65536 ? c->max_items : 65536;
     ItemArgs ia{C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
                 c->epoch};
@@ -1418,7 +1487,10 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
                            a, ia, 1);
         return hipGetLastError();
     }
-    hipError_t e = scan<int64_t>(rooms, C, c->nbase, c->scan_tmp, c->flags, G_FULL, c->epoch, s);
+    hipLaunchKernelGGL(k_room_denom, dim3((C + kScanBlock - 1) / kScanBlock), dim3(256), 0, s, rw,
+                       C, c->room_denom, c->flags, c->epoch);
+    hipError_t e = scan<int64_t>(RoomsDev{rooms, c->room_denom}, C, c->nbase, c->scan_tmp,
+                                 c->flags, G_FULL, c->epoch, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
     hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, a,

@@ -146,6 +146,7 @@ struct st_ctx {
     int32_t *items = nullptr;      // [max_items][2]
     int32_t *nseg = nullptr;       // [C+1] offsets of the work items per chunk
     int64_t *scan_tmp = nullptr;   // block partials of the scans
+    int64_t *room_denom = nullptr; // [1] sum of the chunks' room weights
     int32_t *flags = nullptr;      // DevFlag counters
     void *src = nullptr;           // [C][3][E^3] accumulator (double or float)
     double *stage64 = nullptr;     // staging for host-side injects ([batch][7])

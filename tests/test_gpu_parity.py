@@ -122,6 +122,27 @@ def test_lockstep_crowded_chunk_fills(orc):
     _run_lockstep(orc, w, "fp64", nsteps=9)
 
 
+def test_lockstep_many_chunks_multi_launch_layout(orc):
+    # 2-cell chunks on a 96 x 96 x 64 mesh: 73 728 chunks, more than one
+    # workgroup's scan, so the layout and the rooms of a full re-bin take the
+    # multi-launch path; the second injection forces a full re-bin there
+    w = workload("plume256", n=(96, 96, 64), L=(0.096, 0.096, 0.064), P=200000, plumes=2,
+                 plume_fraction=0.8, chunk_edge=2)
+    t = tracker(w, "fp32_local")
+    x, up, d = w.particles()
+    half = w.P // 2
+    t.inject(x[:half], up[:half], d[:half])
+    Udev, Uor = fields(w, "fp32_local")
+    mesh = oracle_mesh(w)
+    print(lockstep_check(t, orc, mesh, Udev, Uor, 1e-3, 2, TOL["fp32_local"]))
+    t.inject(x[half:], up[half:], d[half:])
+    print(lockstep_check(t, orc, mesh, Udev, Uor, 1e-3, 3, TOL["fp32_local"]))
+    assert t.count() == w.P
+    st = t.stats()
+    assert st["movers"] > 0 and st["repacks"] >= 2, st
+    t.close()
+
+
 def test_free_run_tg32_fp64(orc):
     """Config-0 workload in full (1e5 droplets, 100 steps of 1e-4 s), FP64 form."""
     w = workload("tg32")
