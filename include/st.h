@@ -210,8 +210,9 @@ st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
                    void *hip_stream);
 
 /* Device time of the step kernel (the per-particle gather, integrate,
- * deposit and relocate) measured with HIP events recorded around each of its
- * launches on the launch stream.  enable != 0 starts a measurement (clearing
+ * deposit and relocate) measured with a pair of HIP events attached to each
+ * of its launches (hipExtLaunchKernel), which take the start and end of the
+ * kernel's own execution on the launch stream.  enable != 0 starts a measurement (clearing
  * earlier ones); enable == 0 stops it.  kernel_ms and launches (host, may be
  * NULL) receive the summed milliseconds and the number of launches measured
  * so far; reading them synchronises the recorded events. */

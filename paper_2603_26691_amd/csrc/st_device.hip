@@ -31,6 +31,8 @@
 // the step that raised them, so nothing has to clear them between steps.
 #include "st_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace st {
@@ -1412,27 +1414,33 @@ hipError_t dispatch(st_ctx *c, F &&f)
     }
 }
 
+// ev[0], ev[1] (when not null) take the start and end of the kernel's own
+// execution (not of the commands around it)
 template <class T, class A, int E, int I, int D>
-hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s, hipEvent_t *ev)
 {
     const int64_t round = 8 * kXcdBlock;
     const int64_t grid = (c->max_items + round - 1) / round * round;
-    hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (ev[0])
+        hipExtLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, ev[0],
+                              ev[1], 0, a);
+    else
+        hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 template <class T, class A, int E, int I>
-hipError_t launch_step_d(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+hipError_t launch_step_d(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s, hipEvent_t *ev)
 {
-    return c->prm.drag == 1 ? launch_step_t<T, A, E, I, 1>(c, a, s)
-                            : launch_step_t<T, A, E, I, 0>(c, a, s);
+    return c->prm.drag == 1 ? launch_step_t<T, A, E, I, 1>(c, a, s, ev)
+                            : launch_step_t<T, A, E, I, 0>(c, a, s, ev);
 }
 
 template <class T, class A, int E>
-hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s)
+hipError_t launch_step_e(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s, hipEvent_t *ev)
 {
-    return c->prm.interp == 1 ? launch_step_d<T, A, E, 1>(c, a, s)
-                              : launch_step_d<T, A, E, 0>(c, a, s);
+    return c->prm.interp == 1 ? launch_step_d<T, A, E, 1>(c, a, s, ev)
+                              : launch_step_d<T, A, E, 0>(c, a, s, ev);
 }
 
 template <class T>
@@ -1574,16 +1582,13 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
                 if (ee != hipSuccess) return ee;
                 c->tev.push_back(ev[k]);
             }
-            hipError_t ee = hipEventRecord(ev[0], s);
-            if (ee != hipSuccess) return ee;
         }
         hipError_t r;
         switch (c->prm.E) {
-        case 2: r = launch_step_e<T, A, 2>(c, a, s); break;
-        case 4: r = launch_step_e<T, A, 4>(c, a, s); break;
-        default: r = launch_step_e<T, A, 8>(c, a, s); break;
+        case 2: r = launch_step_e<T, A, 2>(c, a, s, ev); break;
+        case 4: r = launch_step_e<T, A, 4>(c, a, s, ev); break;
+        default: r = launch_step_e<T, A, 8>(c, a, s, ev); break;
         }
-        if (r == hipSuccess && c->timing) r = hipEventRecord(ev[1], s);
         if (r != hipSuccess) return r;
 
         return launch_rebin<T>(c, 0, s);
