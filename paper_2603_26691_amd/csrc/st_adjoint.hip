@@ -58,16 +58,60 @@ struct AdjArgs {
 // workgroups over shorter runs, measured slower).
 constexpr int kAdjBlock = 256;
 
+// Block-wide exclusive scan of one value per thread (kAdjBlock threads);
+// returns the prefix and the block total.
+__device__ int32_t adj_block_scan(int32_t v, int32_t &total)
+{
+    __shared__ int32_t ws[kAdjBlock / 64];
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    int32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    int32_t before = 0;
+    total = 0;
+    for (int k = 0; k < kAdjBlock / 64; ++k) {
+        if (k < wave) before += ws[k];
+        total += ws[k];
+    }
+    __syncthreads();
+    return before + incl - v;
+}
+
+// Particles per batch of the trilinear scatter (their stencil offsets and
+// ufbar wait in LDS, ordered by stencil base): about 70 KB of LDS per
+// workgroup in either form, so that two workgroups share a CU.
+template <class T>
+constexpr int adj_batch() { return sizeof(T) == 4 ? 512 : 256; }
+
 template <class T, int E, int INTERP>
 __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
 {
     constexpr int S = E + 2;
     constexpr int S3 = S * S * S;
     constexpr int E3 = E * E * E;
+    constexpr int E1 = E + 1;
+    constexpr int NB = E1 * E1 * E1;        // trilinear stencil bases (lowest corners)
+    constexpr int B = adj_batch<T>();
+    constexpr bool TRI = INTERP == 0;
     __shared__ T tile[3 * S3];
-    // Ubar over the tile, summed in the state precision: a cell takes a few
-    // dozen terms per step, and every step's sum goes to binary64 globally
-    __shared__ T ubt[3 * S3];
+    // Nearest grid point: Ubar over the tile, summed in the state precision
+    // with one atomic per particle and component.
+    __shared__ T ubt[TRI ? 1 : 3 * S3];
+    // Trilinear: the reverse of the gather is a scatter to 8 corners.  Instead
+    // of 24 LDS atomics per particle (measured to dominate the kernel), the
+    // particles of a batch are ordered by stencil base and every thread sums
+    // the contributions to the tile nodes it owns, in binary64.
+    __shared__ double nacc[TRI ? 3 * S3 : 1];     // node sums, [3][S3]
+    __shared__ double rf[TRI ? 3 * B : 1];        // fractional offsets f
+    __shared__ double ru[TRI ? 3 * B : 1];        // ufbar
+    __shared__ int32_t rb[TRI ? B : 1];           // stencil base, -1 for none
+    __shared__ int32_t perm[TRI ? B : 1];         // batch entries by base
+    __shared__ int32_t bstart[TRI ? NB + 1 : 1];  // first entry of each base
+    __shared__ int32_t bcur[TRI ? NB : 1];        // counts, then cursors
 
     const int64_t item = blockIdx.x;
     if (item >= *a.nitems) return;
@@ -109,7 +153,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             const int t = threadIdx.x + u * kAdjBlock;
             if (t < 3 * S3) {
                 tile[t] = vals[u];
-                ubt[t] = T(0);
+                if (TRI) nacc[t] = 0.0;
+                else ubt[t] = T(0);
             }
         }
     }
@@ -118,106 +163,209 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
     const double dt = a.dt;
     const double inv_V = p.inv_V;
     const double *lam = a.lamC + c * 3 * E3;
-    for (int64_t q = s0 + threadIdx.x; q < s1; q += kAdjBlock) {
-        const int64_t id = a.id[q];
-        if (id < 0 || id >= a.count) continue;  // never in a saved store
-        const double xi[3] = {(double)a.ox[q], (double)a.oy[q], (double)a.oz[q]};
-        const double up[3] = {(double)a.vx[q], (double)a.vy[q], (double)a.vz[q]};
-        const double dp = (double)a.d[q];
-
-        // interpolation stencil in binary64 at the saved position
-        int cl[3], i0[3];
-        double om[3][2], dom[3][2];
-        for (int ax = 0; ax < 3; ++ax) {
-            cl[ax] = min(max((int)xi[ax], 0), E - 1);
-            if (INTERP == 0) {
-                const double s = xi[ax] - 0.5;
-                const double fl = floor(s);
-                i0[ax] = min(max((int)fl, -1), E - 1);
-                const double f = s - fl;
-                om[ax][0] = 1.0 - f;
-                om[ax][1] = f;
-                dom[ax][0] = -p.inv_h[ax];
-                dom[ax][1] = p.inv_h[ax];
+    const int64_t run = TRI ? (int64_t)B : s1 - s0;   // NGP: the whole range at once
+    for (int64_t q0 = s0; q0 < s1; q0 += run) {
+        const int64_t q1 = min(q0 + run, s1);
+        if (TRI) {
+            for (int b = threadIdx.x; b < NB; b += kAdjBlock) bcur[b] = 0;
+            __syncthreads();
+        }
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += kAdjBlock) {
+            const int jb = (int)(q - q0);   // entry in the batch
+            const int64_t id = a.id[q];
+            if (id < 0 || id >= a.count) {  // never in a saved store
+                if (TRI) rb[jb] = -1;
+                continue;
             }
-        }
-        double uf[3] = {0.0, 0.0, 0.0};
-        int tc[8];
-        double w[8];
-        int nk;
-        if (INTERP == 0) {
-            nk = 8;
-            const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
-            for (int k = 0; k < 8; ++k) {
-                const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
-                tc[k] = t0 + (bz * S + by) * S + bx;
-                w[k] = om[0][bx] * om[1][by] * om[2][bz];
-            }
-        } else {
-            nk = 1;
-            tc[0] = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
-            w[0] = 1.0;
-        }
-        for (int k = 0; k < nk; ++k)
-            for (int comp = 0; comp < 3; ++comp) uf[comp] += w[k] * (double)tile[comp * S3 + tc[k]];
+            const double xi[3] = {(double)a.ox[q], (double)a.oy[q], (double)a.oz[q]};
+            const double up[3] = {(double)a.vx[q], (double)a.vy[q], (double)a.vz[q]};
+            const double dp = (double)a.d[q];
 
-        // forward quantities of the step
-        const double tau_s = p.tau_coef * dp * dp;
-        const double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
-        const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
-        const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
-        const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
-        const double tau = tau_s / f;
-        const double mass = p.mass_coef * dp * dp * dp;
-        const double D = tau + dt;
-        double upn[3];
-        for (int ax = 0; ax < 3; ++ax)
-            upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) / D;
-
-        // reverse
-        const int cell = (cl[2] * E + cl[1]) * E + cl[0];
-        double xb[3], ub[3], ufb[3];
-        double mbar = 0.0, taubar = 0.0;
-        double *rec = a.adj + 8 * id;   // one 64-byte record per particle
-        for (int ax = 0; ax < 3; ++ax) {
-            xb[ax] = rec[ax];
-            ub[ax] = rec[3 + ax];
-        }
-        for (int ax = 0; ax < 3; ++ax) {
-            const double Jbar = -lam[ax * E3 + cell] * inv_V;
-            const double wbar = ub[ax] + dt * xb[ax] + mass * Jbar;
-            mbar += Jbar * (upn[ax] - up[ax] - p.g[ax] * dt);
-            ufb[ax] = dt / D * wbar;
-            taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]) / D;
-            ub[ax] = -mass * Jbar + tau / D * wbar;
-        }
-        double Rebar = 0.0;
-        if (Re > 0.0) {
-            Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
+            // interpolation stencil in binary64 at the saved position
+            int cl[3], i0[3];
+            double om[3][2], dom[3][2];
             for (int ax = 0; ax < 3; ++ax) {
-                const double sb = Rebar * Re * slip[ax] / s2;
-                ufb[ax] += sb;
-                ub[ax] -= sb;
+                cl[ax] = min(max((int)xi[ax], 0), E - 1);
+                if (TRI) {
+                    const double s = xi[ax] - 0.5;
+                    const double fl = floor(s);
+                    i0[ax] = min(max((int)fl, -1), E - 1);
+                    const double f = s - fl;
+                    om[ax][0] = 1.0 - f;
+                    om[ax][1] = f;
+                    dom[ax][0] = -p.inv_h[ax];
+                    dom[ax][1] = p.inv_h[ax];
+                }
             }
+            double uf[3] = {0.0, 0.0, 0.0};
+            int tc[8];
+            double w[8];
+            int nk;
+            if (TRI) {
+                nk = 8;
+                const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
+                for (int k = 0; k < 8; ++k) {
+                    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+                    tc[k] = t0 + (bz * S + by) * S + bx;
+                    w[k] = om[0][bx] * om[1][by] * om[2][bz];
+                }
+            } else {
+                nk = 1;
+                tc[0] = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
+                w[0] = 1.0;
+            }
+            for (int k = 0; k < nk; ++k)
+                for (int comp = 0; comp < 3; ++comp)
+                    uf[comp] += w[k] * (double)tile[comp * S3 + tc[k]];
+
+            // forward quantities of the step
+            const double tau_s = p.tau_coef * dp * dp;
+            const double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
+            const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
+            const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
+            const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
+            const double tau = tau_s / f;
+            const double mass = p.mass_coef * dp * dp * dp;
+            const double D = tau + dt;
+            double upn[3];
+            for (int ax = 0; ax < 3; ++ax)
+                upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) / D;
+
+            // reverse
+            const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+            double xb[3], ub[3], ufb[3];
+            double mbar = 0.0, taubar = 0.0;
+            double *rec = a.adj + 8 * id;   // one 64-byte record per particle
+            for (int ax = 0; ax < 3; ++ax) {
+                xb[ax] = rec[ax];
+                ub[ax] = rec[3 + ax];
+            }
+            for (int ax = 0; ax < 3; ++ax) {
+                const double Jbar = -lam[ax * E3 + cell] * inv_V;
+                const double wbar = ub[ax] + dt * xb[ax] + mass * Jbar;
+                mbar += Jbar * (upn[ax] - up[ax] - p.g[ax] * dt);
+                ufb[ax] = dt / D * wbar;
+                taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]) / D;
+                ub[ax] = -mass * Jbar + tau / D * wbar;
+            }
+            double Rebar = 0.0;
+            if (Re > 0.0) {
+                Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
+                for (int ax = 0; ax < 3; ++ax) {
+                    const double sb = Rebar * Re * slip[ax] / s2;
+                    ufb[ax] += sb;
+                    ub[ax] -= sb;
+                }
+            }
+            for (int k = 0; k < nk; ++k) {
+                double dot = 0.0;
+                for (int comp = 0; comp < 3; ++comp) {
+                    if (!TRI) atomicAdd(&ubt[comp * S3 + tc[k]], (T)(w[k] * ufb[comp]));
+                    dot += (double)tile[comp * S3 + tc[k]] * ufb[comp];
+                }
+                if (TRI) {
+                    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+                    xb[0] += dom[0][bx] * om[1][by] * om[2][bz] * dot;
+                    xb[1] += om[0][bx] * dom[1][by] * om[2][bz] * dot;
+                    xb[2] += om[0][bx] * om[1][by] * dom[2][bz] * dot;
+                }
+            }
+            if (TRI) {
+                // the scatter waits for the batch: base, offsets and ufbar
+                const int b = ((i0[2] + 1) * E1 + (i0[1] + 1)) * E1 + (i0[0] + 1);
+                rb[jb] = b;
+                for (int ax = 0; ax < 3; ++ax) {
+                    rf[ax * B + jb] = om[ax][1];
+                    ru[ax * B + jb] = ufb[ax];
+                }
+                atomicAdd(&bcur[b], 1);
+            }
+            for (int ax = 0; ax < 3; ++ax) {
+                rec[ax] = xb[ax];
+                rec[3 + ax] = ub[ax];
+            }
+            rec[6] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
         }
-        for (int k = 0; k < nk; ++k) {
-            double dot = 0.0;
+        if (!TRI) break;
+
+        // order the batch by stencil base (a counting sort in LDS) ...
+        __syncthreads();
+        {
+            constexpr int PER = (NB + kAdjBlock - 1) / kAdjBlock;
+            int32_t v[PER];
+            int32_t sum = 0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int b = threadIdx.x * PER + k;
+                v[k] = b < NB ? bcur[b] : 0;
+                sum += v[k];
+            }
+            int32_t total;
+            int32_t ex = adj_block_scan(sum, total);
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int b = threadIdx.x * PER + k;
+                if (b < NB) {
+                    bstart[b] = ex;
+                    bcur[b] = ex;
+                }
+                ex += v[k];
+            }
+            if (threadIdx.x == 0) bstart[NB] = total;
+        }
+        __syncthreads();
+        for (int jb = threadIdx.x; jb < (int)(q1 - q0); jb += kAdjBlock) {
+            const int b = rb[jb];
+            if (b >= 0) perm[atomicAdd(&bcur[b], 1)] = jb;
+        }
+        __syncthreads();
+        // ... and let every node gather from the (up to 8) bases whose stencil
+        // holds it: node = base + (bx, by, bz), weight prod over the axes of
+        // f (offset 1) or 1 - f (offset 0)
+        for (int n = threadIdx.x; n < S3; n += kAdjBlock) {   // nodes owned by this thread
+            const int nx = n % S, ny = (n / S) % S, nz = n / (S * S);
+            // per row (by, bz) of bases the node's x-neighbours nx - 1 (offset
+            // 1) and nx (offset 0) are adjacent bases, so their entries are
+            // one range [lo, hi), split at mid; all 12 bounds load first
+            const int xa = max(nx - 1, 0), xl = min(nx, E);
+            int lo[4], mid[4], hi[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int y = ny - (k & 1), z = nz - (k >> 1);
+                const bool ok = y >= 0 && z >= 0 && y <= E && z <= E;
+                const int row = (z * E1 + y) * E1;
+                lo[k] = ok ? bstart[row + xa] : 0;
+                hi[k] = ok ? bstart[row + xl + 1] : 0;
+                mid[k] = !ok ? 0 : nx == 0 ? lo[k] : nx > E ? hi[k] : bstart[row + nx];
+            }
+            double sum[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int by = k & 1, bz = k >> 1;
+                for (int e = lo[k]; e < hi[k]; ++e) {
+                    const int jb = perm[e];
+                    const double fx = rf[jb], fy = rf[B + jb], fz = rf[2 * B + jb];
+                    const double wk = (e < mid[k] ? fx : 1.0 - fx) * (by ? fy : 1.0 - fy) *
+                                      (bz ? fz : 1.0 - fz);
+                    sum[0] += wk * ru[jb];
+                    sum[1] += wk * ru[B + jb];
+                    sum[2] += wk * ru[2 * B + jb];
+                }
+            }
+            for (int comp = 0; comp < 3; ++comp) nacc[comp * S3 + n] += sum[comp];
+        }
+        __syncthreads();   // the next batch overwrites the entries
+    }
+    if (TRI) {
+        // each node's sum was last written by this thread
+        for (int n = threadIdx.x; n < S3; n += kAdjBlock) {
+            const int64_t g = tile_cell(n);
             for (int comp = 0; comp < 3; ++comp) {
-                atomicAdd(&ubt[comp * S3 + tc[k]], (T)(w[k] * ufb[comp]));
-                dot += (double)tile[comp * S3 + tc[k]] * ufb[comp];
-            }
-            if (INTERP == 0) {
-                const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
-                xb[0] += dom[0][bx] * om[1][by] * om[2][bz] * dot;
-                xb[1] += om[0][bx] * dom[1][by] * om[2][bz] * dot;
-                xb[2] += om[0][bx] * om[1][by] * dom[2][bz] * dot;
+                const double v = nacc[comp * S3 + n];
+                if (v != 0.0) atomicAdd(a.Ubar + comp * ncell + g, v);
             }
         }
-        for (int ax = 0; ax < 3; ++ax) {
-            rec[ax] = xb[ax];
-            rec[3 + ax] = ub[ax];
-        }
-        rec[6] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
+        return;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) {

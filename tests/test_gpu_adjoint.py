@@ -26,9 +26,9 @@ def _case(P=4000, n=(16, 16, 16), nsteps=30):
     return workload("adj64", n=n, P=P, nsteps=nsteps, noise=0.2)
 
 
-def _forward(w, form, x, up, d, U, K, drag="stokes"):
+def _forward(w, form, x, up, d, U, K, drag="stokes", interp="trilinear"):
     import torch
-    t = tracker(w, form, drag=drag)
+    t = tracker(w, form, drag=drag, interp=interp)
     t.inject(x, up, d)
     s0 = state(t)
     for _ in range(w.nsteps):
@@ -41,8 +41,8 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _target(w, form, x, up, d, U, drag="stokes"):
-    t = tracker(w, form, drag=drag)
+def _target(w, form, x, up, d, U, drag="stokes", interp="trilinear"):
+    t = tracker(w, form, drag=drag, interp=interp)
     t.inject(x, up, d * 1.1)
     for _ in range(w.nsteps):
         t.step(U, w.dt)
@@ -77,6 +77,29 @@ def test_adjoint_matches_oracle(orc, form, tol, drag):
                          w.nsteps, lam)
     eU, ed = _rel(dU, oU), _rel(dd, od)
     print(form, drag, "adjoint rel L2: dU", eU, "dd", ed)
+    assert eU < tol and ed < tol
+    t.close()
+
+
+@pytest.mark.parametrize("form,tol,interp,P", [
+    ("fp64", 1e-9, "ngp", 4000), ("fp32_local", 1e-4, "ngp", 4000),
+    ("fp64", 1e-9, "trilinear", 40000), ("fp32_local", 1e-4, "trilinear", 40000)])
+def test_adjoint_ngp_and_crowded_chunks(orc, form, tol, interp, P):
+    # nearest grid point (one corner per particle); and 5000 droplets per
+    # chunk, so that the trilinear scatter runs over several batches
+    import torch
+    w = _case(P=P, nsteps=12 if P > 10000 else 30)
+    x, up, d = w.particles()
+    Udev, Uor = fields(w, form)
+    T = _target(w, form, x, up, d, Udev, interp=interp)
+    t, s0, S = _forward(w, form, x, up, d, Udev, K=5, interp=interp)
+    lam = 2.0 * (S.cpu().numpy() - T)
+    dU, dd = t.backward(torch.from_numpy(lam).cuda())
+    dU, dd = dU.cpu().numpy(), dd.cpu().numpy()
+    oU, od = orc.adjoint(oracle_mesh(w, interp=1 if interp == "ngp" else 0), Uor, s0["x"],
+                         s0["up"], s0["d"], w.dt, w.nsteps, lam)
+    eU, ed = _rel(dU, oU), _rel(dd, od)
+    print(form, interp, P, "adjoint rel L2: dU", eU, "dd", ed)
     assert eU < tol and ed < tol
     t.close()
 
