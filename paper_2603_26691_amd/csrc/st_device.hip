@@ -754,20 +754,37 @@ __global__ void __launch_bounds__(kBlock)
         vst<T, G>(at_byte(pvx, ob), UX);
         vst<T, G>(at_byte(pvy, ob), UY);
         vst<T, G>(at_byte(pvz, ob), UZ);
-        // stage the movers with their direction class and rank in it
-        while (movers) {
-            const int k = __ffs(movers) - 1;
-            movers &= movers - 1;
-            const int j = atomicAdd(&mcount, 1);
-            if (j < kMoverStage) {
-                const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
-                const int rank = atomicAdd(&dcount[dir], 1);
-                mstage[j] = (int32_t)(o + k) | (dir << kSlotBits) |
-                            (rank << (kSlotBits + kDirBits));
-            } else {  // more movers than the LDS stage holds: emit directly
-                const int64_t m = atomicAdd(a.nmov, 1);
-                const int64_t h = atomicAdd(&a.out_cnt[c], 1);
-                emit_mover(a, c, base, s0 + o + k, m, h);
+        // stage the movers with their direction class: one reservation of
+        // stage entries per wave (their ranks within the direction classes
+        // are taken after the loop)
+        if (__ballot(movers != 0)) {
+            // prefix of the lanes' mover counts (at most G < 8) from one
+            // ballot per bit; the first active lane reserves for the wave
+            const int mine = __popc(movers);
+            const uint64_t below = lanes_below_mask();
+            int ex = 0, tot = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const uint64_t bal = __ballot((mine >> b) & 1);
+                ex += __popcll(bal & below) << b;
+                tot += __popcll(bal) << b;
+            }
+            const int first = __ffsll((long long)__ballot(1)) - 1;
+            int j0 = 0;
+            if (__lane_id() == first) j0 = atomicAdd(&mcount, tot);
+            int j = __shfl(j0, first) + ex;
+            while (movers) {
+                const int k = __ffs(movers) - 1;
+                movers &= movers - 1;
+                if (j < kMoverStage) {
+                    const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
+                    mstage[j] = (int32_t)(o + k) | (dir << kSlotBits);
+                } else {  // more movers than the LDS stage holds: emit directly
+                    const int64_t m = atomicAdd(a.nmov, 1);
+                    const int64_t h = atomicAdd(&a.out_cnt[c], 1);
+                    emit_mover(a, c, base, s0 + o + k, m, h);
+                }
+                ++j;
             }
         }
 #pragma unroll
@@ -792,6 +809,15 @@ __global__ void __launch_bounds__(kBlock)
     // counters of crowded chunks.  The movers' state is read in the same
     // round trip.
     const int nm = min(mcount, kMoverStage);
+    // ranks of the staged movers within their direction classes
+    if (nm > 0) {
+        for (int j = threadIdx.x; j < nm; j += kBlock) {
+            const int32_t w = mstage[j];
+            const int dir = (w >> kSlotBits) & ((1 << kDirBits) - 1);
+            mstage[j] = w | (atomicAdd(&dcount[dir], 1) << (kSlotBits + kDirBits));
+        }
+        __syncthreads();
+    }
     // The chunk's source cells are read first (a chunk that is one work item
     // adds its sum to them; one split over several items adds atomically).
     A *const src_c = a.src + c * (3 * E3);
