@@ -170,16 +170,45 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             for (int b = threadIdx.x; b < NB; b += kAdjBlock) bcur[b] = 0;
             __syncthreads();
         }
-        for (int64_t q = q0 + threadIdx.x; q < q1; q += kAdjBlock) {
+        // a thread's particles of the batch (PPT of them) load first: ids and
+        // saved states, then the adjoint records the ids address
+        constexpr int PPT = TRI ? B / kAdjBlock : 1;
+        for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += (int64_t)PPT * kAdjBlock) {
+        int64_t idv[PPT];
+        T ls[PPT][7];
+        double lr[PPT][7];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int64_t q = qb + (int64_t)u * kAdjBlock;
+            idv[u] = -1;
+            if (q < q1) {
+                idv[u] = a.id[q];
+                ls[u][0] = a.ox[q];
+                ls[u][1] = a.oy[q];
+                ls[u][2] = a.oz[q];
+                ls[u][3] = a.vx[q];
+                ls[u][4] = a.vy[q];
+                ls[u][5] = a.vz[q];
+                ls[u][6] = a.d[q];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u)
+            if (idv[u] >= 0 && idv[u] < a.count)
+                for (int k = 0; k < 7; ++k) lr[u][k] = a.adj[8 * idv[u] + k];
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int64_t q = qb + (int64_t)u * kAdjBlock;
+            if (q >= q1) continue;
             const int jb = (int)(q - q0);   // entry in the batch
-            const int64_t id = a.id[q];
+            const int64_t id = idv[u];
             if (id < 0 || id >= a.count) {  // never in a saved store
                 if (TRI) rb[jb] = -1;
                 continue;
             }
-            const double xi[3] = {(double)a.ox[q], (double)a.oy[q], (double)a.oz[q]};
-            const double up[3] = {(double)a.vx[q], (double)a.vy[q], (double)a.vz[q]};
-            const double dp = (double)a.d[q];
+            const double xi[3] = {(double)ls[u][0], (double)ls[u][1], (double)ls[u][2]};
+            const double up[3] = {(double)ls[u][3], (double)ls[u][4], (double)ls[u][5]};
+            const double dp = (double)ls[u][6];
 
             // interpolation stencil in binary64 at the saved position
             int cl[3], i0[3];
@@ -237,8 +266,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             double mbar = 0.0, taubar = 0.0;
             double *rec = a.adj + 8 * id;   // one 64-byte record per particle
             for (int ax = 0; ax < 3; ++ax) {
-                xb[ax] = rec[ax];
-                ub[ax] = rec[3 + ax];
+                xb[ax] = lr[u][ax];
+                ub[ax] = lr[u][3 + ax];
             }
             for (int ax = 0; ax < 3; ++ax) {
                 const double Jbar = -lam[ax * E3 + cell] * inv_V;
@@ -284,7 +313,9 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
                 rec[ax] = xb[ax];
                 rec[3 + ax] = ub[ax];
             }
-            rec[6] += taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp + mbar * 3.0 * mass / dp;
+            rec[6] = lr[u][6] + taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp +
+                     mbar * 3.0 * mass / dp;
+        }
         }
         if (!TRI) break;
 
