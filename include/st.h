@@ -152,7 +152,8 @@ st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
  * to the time-integrated source accumulated by the taped steps.  Writes
  * dL/du (device, [3][n2][n1][n0] binary64; the sum over the taped steps'
  * fields, which are one tensor when every step used the same field) and
- * dL/dd (device, [count] binary64, by id).  Checkpoints are restored and
+ * dL/dd (device, [count] binary64, by id; may be NULL when count is 0).
+ * Checkpoints are restored and
  * the steps between them recomputed.  The tape is consumed.  ST_ERR_STATE
  * if nothing is taped. */
 st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,

@@ -408,7 +408,8 @@ st_status st_backward(st_ctx *c, const double *dL_dSint, double *dL_du, double *
                       void *hip_stream)
 {
     if (!c) return ST_ERR_INVALID;
-    if (!dL_dSint || !dL_du || !dL_dd) return fail(c, ST_ERR_INVALID, "st_backward: null pointer");
+    if (!dL_dSint || !dL_du || (!dL_dd && c->count > 0))
+        return fail(c, ST_ERR_INVALID, "st_backward: null pointer");
     if (c->tape.empty()) return fail(c, ST_ERR_STATE, "st_backward: nothing taped");
     ST_HIP(hipSetDevice(c->device));
     ST_HIP(st::launch_backward(c, dL_dSint, dL_du, dL_dd, (hipStream_t)hip_stream));
