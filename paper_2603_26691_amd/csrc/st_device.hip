@@ -482,19 +482,29 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid)
     return ((k / kXcdBlock) * 8 + x) * kXcdBlock + k % kXcdBlock;
 }
 
-// G consecutive values at a G*sizeof(T)-aligned address
+// G consecutive values at a G*sizeof(T)-aligned address, as one 16-byte
+// access with the non-temporal hint: the particle state is streamed, read
+// once and written once per step, so it should not displace what the caches
+// hold (the tile, the counters, the mover lists).  Measured: 13 % less step
+// kernel time on 1e7 particles, 11 % on 1.4e9.
 template <class T, int G>
 __device__ __forceinline__ void vld(const T *p, T (&v)[G])
 {
-    const T *q = (const T *)__builtin_assume_aligned(p, G * sizeof(T));
-    __builtin_memcpy(v, q, G * sizeof(T));
+    typedef T vec __attribute__((ext_vector_type(G)));
+    const vec r =
+        __builtin_nontemporal_load((const vec *)__builtin_assume_aligned(p, G * sizeof(T)));
+#pragma unroll
+    for (int k = 0; k < G; ++k) v[k] = r[k];
 }
 
 template <class T, int G>
 __device__ __forceinline__ void vst(T *p, const T (&v)[G])
 {
-    T *q = (T *)__builtin_assume_aligned(p, G * sizeof(T));
-    __builtin_memcpy(q, v, G * sizeof(T));
+    typedef T vec __attribute__((ext_vector_type(G)));
+    vec r;
+#pragma unroll
+    for (int k = 0; k < G; ++k) r[k] = v[k];
+    __builtin_nontemporal_store(r, (vec *)__builtin_assume_aligned(p, G * sizeof(T)));
 }
 
 // base + byte offset: a uniform 64-bit base plus a 32-bit per-lane offset,
