@@ -1519,7 +1519,9 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
     const int64_t total = c->count + npend;
     const RoomWeight rw{c->new_cnt, {c->prm.nc[0], c->prm.nc[1], c->prm.nc[2]}};
     const Rooms rooms{rw, c->slots - total - (int64_t)kAlign * C, 0, c->nroom};
-    const int64_t gs = c->max_items < 65536 ? c->max_items : 65536;
+    // the full re-bin launches run every step and usually exit at their gate:
+    // grids of at most 2048 workgroups (strided loops) keep that cheap
+    const int64_t gs = c->max_items < 2048 ? c->max_items : 2048;
     ItemArgs ia{C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
                 c->epoch};
     if (C <= kScan1Max) {
@@ -1527,7 +1529,7 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
         hipLaunchKernelGGL(k_layout1, dim3(1), dim3(1024), 0, s, rooms, c->nbase,
                            Segments{c->cnt}, Segments{c->new_cnt}, ia, c->flags);
         hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 2048)), dim3(256), 0, s,
                            a, ia, 1);
         return hipGetLastError();
     }
@@ -1537,7 +1539,7 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
                                  c->flags, G_FULL, c->epoch, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s, a,
+    hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 2048)), dim3(256), 0, s, a,
                        ia, 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
