@@ -569,6 +569,11 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ T tile[3 * S3];
     __shared__ A acc[3 * E3];
     __shared__ int32_t mstage[kMoverStage];
+    // binary32 state: the staged movers' new positions and velocities (12 KB,
+    // which still lets four workgroups share a CU; the binary64 form re-reads
+    // them instead)
+    constexpr bool kStageVals = sizeof(T) == 4;
+    __shared__ T mval[kStageVals ? 6 * kMoverStage : 1];
     __shared__ int32_t mcount, mbase_sh, hbase_sh;
     __shared__ int32_t dcount[28], doff[28], dbase[27], nb_free[27];
     __shared__ int64_t nb_base[27];
@@ -783,18 +788,41 @@ __global__ void __launch_bounds__(kBlock)
             int j0 = 0;
             if (__lane_id() == first) j0 = atomicAdd(&mcount, tot);
             int j = __shfl(j0, first) + ex;
-            while (movers) {
-                const int k = __ffs(movers) - 1;
-                movers &= movers - 1;
-                if (j < kMoverStage) {
-                    const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
-                    mstage[j] = (int32_t)(o + k) | (dir << kSlotBits);
-                } else {  // more movers than the LDS stage holds: emit directly
-                    const int64_t m = atomicAdd(a.nmov, 1);
-                    const int64_t h = atomicAdd(&a.out_cnt[c], 1);
-                    emit_mover(a, c, base, s0 + o + k, m, h);
+            if constexpr (kStageVals) {
+                // binary32: the new state too, so that it need not be re-read
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    if (!((movers >> k) & 1)) continue;
+                    if (j < kMoverStage) {
+                        const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
+                        mstage[j] = (int32_t)(o + k) | (dir << kSlotBits);
+                        mval[j] = X[k];
+                        mval[kMoverStage + j] = Y[k];
+                        mval[2 * kMoverStage + j] = Z[k];
+                        mval[3 * kMoverStage + j] = UX[k];
+                        mval[4 * kMoverStage + j] = UY[k];
+                        mval[5 * kMoverStage + j] = UZ[k];
+                    } else {  // more movers than the LDS stage holds: emit directly
+                        const int64_t m = atomicAdd(a.nmov, 1);
+                        const int64_t h = atomicAdd(&a.out_cnt[c], 1);
+                        emit_mover(a, c, base, s0 + o + k, m, h);
+                    }
+                    ++j;
                 }
-                ++j;
+            } else {
+                while (movers) {
+                    const int k = __ffs(movers) - 1;
+                    movers &= movers - 1;
+                    if (j < kMoverStage) {
+                        const int dir = (dirs >> (kDirBits * k)) & ((1 << kDirBits) - 1);
+                        mstage[j] = (int32_t)(o + k) | (dir << kSlotBits);
+                    } else {  // more movers than the LDS stage holds: emit directly
+                        const int64_t m = atomicAdd(a.nmov, 1);
+                        const int64_t h = atomicAdd(&a.out_cnt[c], 1);
+                        emit_mover(a, c, base, s0 + o + k, m, h);
+                    }
+                    ++j;
+                }
             }
         }
 #pragma unroll
@@ -849,12 +877,21 @@ __global__ void __launch_bounds__(kBlock)
         const int j = threadIdx.x + u * kBlock;
         if (j < nm) {
             const int64_t q = s0 + (mstage[j] & ((1 << kSlotBits) - 1));
-            mx[u] = V.ox[q];
-            my[u] = V.oy[q];
-            mz[u] = V.oz[q];
-            mvx[u] = V.vx[q];
-            mvy[u] = V.vy[q];
-            mvz[u] = V.vz[q];
+            if constexpr (kStageVals) {
+                mx[u] = mval[j];
+                my[u] = mval[kMoverStage + j];
+                mz[u] = mval[2 * kMoverStage + j];
+                mvx[u] = mval[3 * kMoverStage + j];
+                mvy[u] = mval[4 * kMoverStage + j];
+                mvz[u] = mval[5 * kMoverStage + j];
+            } else {
+                mx[u] = V.ox[q];
+                my[u] = V.oy[q];
+                mz[u] = V.oz[q];
+                mvx[u] = V.vx[q];
+                mvy[u] = V.vy[q];
+                mvz[u] = V.vz[q];
+            }
             md[u] = V.d[q];
             mid[u] = V.id[q];
         }
