@@ -82,10 +82,11 @@ __device__ int32_t adj_block_scan(int32_t v, int32_t &total)
 }
 
 // Particles per batch of the trilinear scatter (their stencil offsets and
-// ufbar wait in LDS, ordered by stencil base): about 70 KB of LDS per
-// workgroup in either form, so that two workgroups share a CU.
+// ufbar wait in LDS, in the state precision, ordered by stencil base): about
+// 70 KB of LDS per workgroup in either form, so that two workgroups share a
+// CU.
 template <class T>
-constexpr int adj_batch() { return sizeof(T) == 4 ? 512 : 256; }
+constexpr int adj_batch() { return sizeof(T) == 4 ? 1024 : 256; }
 
 template <class T, int E, int INTERP>
 __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
@@ -106,12 +107,12 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
     // particles of a batch are ordered by stencil base and every thread sums
     // the contributions to the tile nodes it owns, in binary64.
     __shared__ double nacc[TRI ? 3 * S3 : 1];     // node sums, [3][S3]
-    __shared__ double rf[TRI ? 3 * B : 1];        // fractional offsets f
-    __shared__ double ru[TRI ? 3 * B : 1];        // ufbar
-    __shared__ int32_t rb[TRI ? B : 1];           // stencil base, -1 for none
+    __shared__ T rf[TRI ? 3 * B : 1];             // fractional offsets f
+    __shared__ T ru[TRI ? 3 * B : 1];             // ufbar
+    __shared__ int32_t rb[TRI ? B : 1];           // base | rank in it << 12, -1 for none
     __shared__ int32_t perm[TRI ? B : 1];         // batch entries by base
     __shared__ int32_t bstart[TRI ? NB + 1 : 1];  // first entry of each base
-    __shared__ int32_t bcur[TRI ? NB : 1];        // counts, then cursors
+    __shared__ int32_t bcur[TRI ? NB : 1];        // entries per base
 
     const int64_t item = blockIdx.x;
     if (item >= *a.nitems) return;
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
         }
         // a thread's particles of the batch (PPT of them) load first: ids and
         // saved states, then the adjoint records the ids address
-        constexpr int PPT = TRI ? B / kAdjBlock : 1;
+        constexpr int PPT = TRI ? 2 : 1;
         for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += (int64_t)PPT * kAdjBlock) {
         int64_t idv[PPT];
         T ls[PPT][7];
@@ -302,12 +303,11 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             if (TRI) {
                 // the scatter waits for the batch: base, offsets and ufbar
                 const int b = ((i0[2] + 1) * E1 + (i0[1] + 1)) * E1 + (i0[0] + 1);
-                rb[jb] = b;
                 for (int ax = 0; ax < 3; ++ax) {
-                    rf[ax * B + jb] = om[ax][1];
-                    ru[ax * B + jb] = ufb[ax];
+                    rf[ax * B + jb] = (T)om[ax][1];
+                    ru[ax * B + jb] = (T)ufb[ax];
                 }
-                atomicAdd(&bcur[b], 1);
+                rb[jb] = b | (atomicAdd(&bcur[b], 1) << 12);
             }
             for (int ax = 0; ax < 3; ++ax) {
                 rec[ax] = xb[ax];
@@ -336,18 +336,15 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int b = threadIdx.x * PER + k;
-                if (b < NB) {
-                    bstart[b] = ex;
-                    bcur[b] = ex;
-                }
+                if (b < NB) bstart[b] = ex;
                 ex += v[k];
             }
             if (threadIdx.x == 0) bstart[NB] = total;
         }
         __syncthreads();
         for (int jb = threadIdx.x; jb < (int)(q1 - q0); jb += kAdjBlock) {
-            const int b = rb[jb];
-            if (b >= 0) perm[atomicAdd(&bcur[b], 1)] = jb;
+            const int32_t w = rb[jb];
+            if (w >= 0) perm[bstart[w & 4095] + (w >> 12)] = jb;
         }
         __syncthreads();
         // ... and let every node gather from the (up to 8) bases whose stencil
@@ -375,12 +372,13 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
                 const int by = k & 1, bz = k >> 1;
                 for (int e = lo[k]; e < hi[k]; ++e) {
                     const int jb = perm[e];
-                    const double fx = rf[jb], fy = rf[B + jb], fz = rf[2 * B + jb];
+                    const double fx = (double)rf[jb], fy = (double)rf[B + jb],
+                                 fz = (double)rf[2 * B + jb];
                     const double wk = (e < mid[k] ? fx : 1.0 - fx) * (by ? fy : 1.0 - fy) *
                                       (bz ? fz : 1.0 - fz);
-                    sum[0] += wk * ru[jb];
-                    sum[1] += wk * ru[B + jb];
-                    sum[2] += wk * ru[2 * B + jb];
+                    sum[0] += wk * (double)ru[jb];
+                    sum[1] += wk * (double)ru[B + jb];
+                    sum[2] += wk * (double)ru[2 * B + jb];
                 }
             }
             for (int comp = 0; comp < 3; ++comp) nacc[comp * S3 + n] += sum[comp];
