@@ -192,8 +192,16 @@ def leg_adjoint(pkg, torch, np, synth):
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
     t.close()
+    value = w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3)
+    # byte model of forward + adjoint with recomputation, per particle-step:
+    # forward 52, recompute with the saved state 52 + 24, reverse 28 (saved
+    # state) + 48 (position and velocity adjoints) + 8 (diameter adjoint) + 4
+    model_b = 216
     return {"workload": w.name, "particles": w.P, "steps": w.nsteps, "checkpoint_every": 20,
-            "value": w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3), "unit": "particle-steps/s",
+            "value": value, "unit": "particle-steps/s",
+            "model_bytes_per_particle_step": model_b,
+            "model_GBps": value * model_b / 1e9,
+            "model_frac_of_peak": value * model_b / 1e9 / HBM_PEAK_GBS,
             "forward_ms": fwd_ms, "backward_ms": bwd_ms,
             "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all())}
 
