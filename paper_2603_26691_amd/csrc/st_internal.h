@@ -165,7 +165,7 @@ struct st_ctx {
     double *ec_prev = nullptr;     // S_last of the previous call
     double *ec_ext = nullptr;      // extrapolation made at the previous call
 
-    // step-kernel timing (events recorded around each launch)
+    // step-kernel timing (a pair of events attached to each launch)
     int timing = 0;
     std::vector<hipEvent_t> tev;   // pairs: start, stop
 
