@@ -51,3 +51,80 @@ def test_precision_study():
     assert rows["fp64"][0] < 1e-12 and rows["fp64"][3] < 1e-12
     assert rows["fp32_local"][0] < 1e-5 and rows["fp32_local"][1] < 1e-5
     assert rows["fp32"][0] < 1e-4
+
+
+def test_precision_study_full_size():
+    """The precision study at its full size: 256^3 mesh, 2e8 droplets in 4
+    plumes, 20 steps.  The oracle cannot step 2e8 droplets, so the binary64
+    form serves as the reference for all of them, and that form is itself
+    checked against the oracle on 20 000 droplets sampled by id, advanced
+    by the oracle from their binary64 initial state over all 20 steps.
+    Reported per binary32 form, over every droplet and cell: worst position
+    error (per L), worst velocity error (m/s), worst per-cell source error
+    (per the largest cell), cell indices that differ from the binary64
+    form's, and the global momentum drift."""
+    import torch
+    w = workload("plume256")
+    L = np.array(w.L)
+    U = w.field()
+    rng = np.random.default_rng(256)
+    sample = np.sort(rng.choice(w.P, 20_000, replace=False))
+    bsz = 1 << 25
+    s_x, s_d = [], []
+    ref = None
+    rows = {}
+    for form in ("fp64", "fp32_local", "fp32"):
+        t = tracker(w, form)
+        for b in range(w.n_device_batches(bsz)):
+            x, up, d = w.device_batch(b, bsz)
+            if form == "fp64":
+                sel = sample[(sample >= b * bsz) & (sample < (b + 1) * bsz)] - b * bsz
+                ix = torch.from_numpy(sel).cuda()
+                s_x.append(x[ix].cpu().numpy())
+                s_d.append(d[ix].cpu().numpy())
+            t.inject(x, up, d)
+            del x, up, d
+        Ud = torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
+        for _ in range(w.nsteps):
+            t.step(Ud, w.dt)
+        s = t.particles()
+        S = t.sources()
+        assert torch.equal(s["id"], torch.arange(w.P, device="cuda"))
+        m = (w.parcel_weight * w.rho_p * np.pi / 6.0) * s["d"] ** 3
+        mv = m[:, None] * s["up"]           # droplets start at rest
+        g = torch.tensor(w.g, dtype=torch.float64, device="cuda")
+        drift = (S.reshape(3, -1).sum(dim=1) * float(np.prod(w.h)) + mv.sum(dim=0)
+                 - w.nsteps * w.dt * g * m.sum())
+        drift = float((drift.abs() / mv.abs().sum(dim=0)).max())
+        if form == "fp64":
+            xs, ds = np.concatenate(s_x), np.concatenate(s_d)
+            orc = load_oracle()
+            xo, uo, _ = orc.run(oracle_mesh(w), U, xs, np.zeros_like(xs), ds, w.dt, w.nsteps)
+            ix = torch.from_numpy(sample).cuda()
+            pos = np.abs(min_image(s["x"][ix].cpu().numpy() - xo, L)).max() / L.max()
+            vel = np.abs(s["up"][ix].cpu().numpy() - uo).max()
+            print(f"\nfp64 form against the oracle on {sample.size} droplets: "
+                  f"pos/L {pos:.3e}, vel {vel:.3e} m/s, momentum drift {drift:.3e}")
+            assert pos < 1e-12 and vel < 1e-12 and drift < 1e-12
+            ref = {"x": s["x"], "up": s["up"], "cell": s["cell"], "S": S}
+            del s
+        else:
+            Lt = torch.tensor(L, dtype=torch.float64, device="cuda")
+            dx = s["x"] - ref["x"]
+            dx = dx - torch.round(dx / Lt) * Lt
+            pos = float(dx.abs().max()) / L.max()
+            vel = float((s["up"] - ref["up"]).abs().max())
+            src = max(float((S[c] - ref["S"][c]).abs().max() / ref["S"][c].abs().max())
+                      for c in range(3))
+            cells = int((s["cell"] != ref["cell"]).any(dim=1).sum())
+            rows[form] = (pos, vel, src, cells, drift)
+            del s, dx
+        t.close()
+        del S, Ud
+        torch.cuda.empty_cache()
+    print("form        pos/L      vel[m/s]   src/max    cells differing  momentum drift")
+    for form, r in rows.items():
+        print(f"{form:10s} {r[0]:.3e}  {r[1]:.3e}  {r[2]:.3e}  {r[3]:15d}  {r[4]:.3e}")
+    assert rows["fp32_local"][0] < 1e-5 and rows["fp32_local"][1] < 1e-5
+    assert rows["fp32"][0] < 1e-4
+    assert rows["fp32_local"][4] < 1e-6
