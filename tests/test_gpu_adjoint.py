@@ -201,3 +201,53 @@ def test_autograd_function():
     assert _rel(dd.grad.cpu().numpy(), gd) < 1e-12
     run.tracker.close()
     t2.close()
+
+
+def test_adjoint_full_size(orc):
+    """Forward + adjoint at the differentiation workload's full size: 64^3,
+    1e6 droplets, 200 steps of 5e-5 s, checkpoints every 20, FP32
+    chunk-local forward.  A droplet's dL/dd depends only on its own
+    trajectory and on dL/dS_int, so the oracle adjoint of 2000 droplets
+    sampled by id, with the full dL/dS_int, checks dL/dd on them; droplets
+    that the oracle's trajectory brings within 1e-4 cell widths of a face at
+    the start of some step (where the binary32 forward may deposit into the
+    neighbouring cell) are excluded and counted.  dL/du is a sum over every
+    droplet and is checked against the FP64 form's adjoint of the same
+    problem (same field, same dL/dS_int), which the smaller cases pin to
+    the oracle."""
+    import torch
+    w = workload("adj64")
+    x, up, d = w.particles()
+    Udev, Uor = fields(w, "fp32_local")
+    T = _target(w, "fp32_local", x, up, d, Udev)
+    t, s0, S = _forward(w, "fp32_local", x, up, d, Udev, K=20)
+    lam = 2.0 * (S.cpu().numpy() - T)
+    lam_dev = torch.from_numpy(lam).cuda()
+    dU, dd = [g.cpu().numpy() for g in t.backward(lam_dev)]
+    t.close()
+    t64, _, _ = _forward(w, "fp64", x, up, d, torch.from_numpy(Uor).cuda(), K=20)
+    dU64, dd64 = [g.cpu().numpy() for g in t64.backward(lam_dev)]
+    t64.close()
+    eU = _rel(dU, dU64)
+
+    rng = np.random.default_rng(64)
+    idx = np.sort(rng.choice(w.P, 2000, replace=False))
+    xs, us, ds = s0["x"][idx], s0["up"][idx], s0["d"][idx]
+    mesh = oracle_mesh(w)
+    h = np.asarray(w.h)
+    near = np.zeros(idx.size, dtype=bool)
+    xo, uo = xs, us
+    for _ in range(w.nsteps):
+        q = xo / h
+        f = q - np.floor(q)
+        near |= (np.minimum(f, 1.0 - f) < 1e-4).any(axis=1)
+        xo, uo, _ = orc.run(mesh, Uor, xo, uo, ds, w.dt, 1)
+    _, od = orc.adjoint(mesh, Uor, xs, us, ds, w.dt, w.nsteps, lam)
+    keep = ~near
+    ed = _rel(dd[idx][keep], od[keep])
+    ed64 = _rel(dd[idx][keep], dd64[idx][keep])
+    print(f"full size: dL/du against the FP64 form {eU:.3e}; dL/dd against the oracle "
+          f"{ed:.3e} on {int(keep.sum())} of {idx.size} sampled droplets "
+          f"({int(near.sum())} near a face excluded), against the FP64 form {ed64:.3e}")
+    assert keep.sum() > idx.size // 2
+    assert eU < 1e-4 and ed < 1e-4
