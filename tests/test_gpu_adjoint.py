@@ -251,3 +251,81 @@ def test_adjoint_full_size(orc):
           f"({int(near.sum())} near a face excluded), against the FP64 form {ed64:.3e}")
     assert keep.sum() > idx.size // 2
     assert eU < 1e-4 and ed < 1e-4
+
+
+def test_finite_differences_full_size():
+    """Central differences (h = 1e-3 relative for diameters, 1e-6 m/s for
+    field entries) of the GPU's FP64 forward at the differentiation
+    workload's full size (64^3, 1e6 droplets, 200 steps) on 32 entries: 16
+    random diameters and 16 field entries taken in order of decreasing
+    gradient, against its adjoint with checkpoints every 20 steps.  An entry
+    whose perturbed runs change any droplet's cell at any step is skipped,
+    counted and replaced by the next one (the deposit cell is piecewise
+    constant); at most 64 entries of each kind are tried.  A field entry
+    moves every droplet near its node, dozens of them here: at 1e-3 m/s one
+    of them crosses a face in the perturbed runs for nearly every entry,
+    hence the smaller step, at which binary64 central differences are still
+    accurate to far below the tolerance."""
+    hU = 1e-6
+    import torch
+    w = workload("adj64")
+    x, up, d = w.particles()
+    Udev, _ = fields(w, "fp64")
+    T = torch.from_numpy(_target(w, "fp64", x, up, d, Udev)).cuda()
+
+    def run(dd, U, base=None):
+        t = tracker(w, "fp64")
+        t.inject(x, up, dd)
+        cells, same = [], True
+        for k in range(w.nsteps):
+            c = t.particles()["cell"]
+            if base is None:
+                cells.append(c)
+            elif same:
+                same = torch.equal(c, base[k])
+            t.step(U, w.dt)
+        Lv = float(((t.sources() - T) ** 2).sum())
+        t.close()
+        return Lv, (cells if base is None else same)
+
+    t, _, S = _forward(w, "fp64", x, up, d, Udev, K=20)
+    lam = (2.0 * (S - T)).contiguous()
+    dU, dd = (g.cpu().numpy() for g in t.backward(lam))
+    t.close()
+    _, cells0 = run(d, Udev)
+    rng = np.random.default_rng(64)
+    checked = skipped = 0
+    for p in rng.choice(w.P, 64, replace=False):
+        if checked == 16:
+            break
+        h = 1e-3 * d[p]
+        dp_, dm_ = d.copy(), d.copy()
+        dp_[p] += h
+        dm_[p] -= h
+        Lp, sp = run(dp_, Udev, cells0)
+        Lm, sm = run(dm_, Udev, cells0)
+        if not (sp and sm):
+            skipped += 1
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - dd[p]) <= 2e-4 * abs(fd) + 1e-6 * np.abs(dd).max(), (p, fd, dd[p])
+        checked += 1
+    n_dd = checked
+    for q in np.argsort(-np.abs(dU).ravel())[:64]:
+        if checked == n_dd + 16:
+            break
+        idx = np.unravel_index(q, dU.shape)
+        Up, Um = Udev.clone(), Udev.clone()
+        Up[idx] += hU
+        Um[idx] -= hU
+        Lp, sp = run(d, Up, cells0)
+        Lm, sm = run(d, Um, cells0)
+        if not (sp and sm):
+            skipped += 1
+            continue
+        fd = (Lp - Lm) / (2 * hU)
+        assert abs(fd - dU[idx]) <= 2e-4 * abs(fd) + 1e-6 * np.abs(dU).max(), (idx, fd, dU[idx])
+        checked += 1
+    print("full-size FD checked", n_dd, "diameters and", checked - n_dd, "field entries;",
+          "skipped", skipped)
+    assert n_dd == 16 and checked == 32
