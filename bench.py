@@ -177,6 +177,16 @@ def leg_adjoint(pkg, torch, np, synth):
         tw.step(U, w.dt, tape=2)
     tw.backward(2.0 * tw.sources())
     tw.close()
+    # the loss's target: the source field of the same droplets with their
+    # diameters scaled by 1.1 (input preparation, untimed)
+    tt = make_tracker(pkg, w, "fp32_local")
+    for b in range(w.n_batches()):
+        x, up, d = w.batch(b)
+        tt.inject(x, up, d * 1.1)
+    for _ in range(w.nsteps):
+        tt.step(U, w.dt)
+    T = tt.sources()
+    tt.close()
     t = make_tracker(pkg, w, "fp32_local")
     inject_host(t, w)
     torch.cuda.synchronize()
@@ -186,12 +196,23 @@ def leg_adjoint(pkg, torch, np, synth):
         t.step(U, w.dt, tape=20)
     S = t.sources()
     e1.record()
-    lam = (2.0 * S).contiguous()  # dL/dS of L = |S|^2, a stand-in for the misfit
+    lam = (2.0 * (S - T)).contiguous()  # dL/dS of L = |S - T|^2
     dU, dd = t.backward(lam)
     e2.record()
     torch.cuda.synchronize()
     fwd_ms, bwd_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
     t.close()
+    # the same problem in the FP64 form (the field widened from binary32, the
+    # same dL/dS), untimed: how far the binary32 forward moves the gradient
+    t64 = make_tracker(pkg, w, "fp64")
+    inject_host(t64, w)
+    U64 = U.double()
+    for _ in range(w.nsteps):
+        t64.step(U64, w.dt, tape=20)
+    dU64, dd64 = t64.backward(lam)
+    t64.close()
+    rel = {"dL_du": float((dU - dU64).norm() / dU64.norm()),
+           "dL_dd": float((dd - dd64).norm() / dd64.norm())}
     value = w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3)
     # byte model of forward + adjoint with recomputation, per particle-step:
     # forward 52, recompute with the saved state 52 + 24, reverse 28 (saved
@@ -203,7 +224,9 @@ def leg_adjoint(pkg, torch, np, synth):
             "model_GBps": value * model_b / 1e9,
             "model_frac_of_peak": value * model_b / 1e9 / HBM_PEAK_GBS,
             "forward_ms": fwd_ms, "backward_ms": bwd_ms,
-            "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all())}
+            "loss": "L2 misfit of the source field against that of diameters x 1.1",
+            "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all()),
+            "grad_rel_l2_vs_fp64_form": rel}
 
 
 def leg_hilbert(pkg, torch, np, w, reps=10):
