@@ -103,6 +103,8 @@ class Oracle:
             "or_run": (None, [M, _P, _I64, _P, _P, _P, _D, _I32, _I32, _P]),
             "or_run_rotating": (None, [M, _P, _P, _I64, _P, _P, _P, _D, _I32, _P]),
             "or_adjoint": (ctypes.c_int, [M, _P, _I64, _P, _P, _P, _D, _I32, _P, _P, _P]),
+            "or_adjoint_run": (ctypes.c_int, [M, _I32, _P, _I32, _P, _P, _I32, _I64, _P, _P,
+                                              _P, _P, _P, _P]),
             "or_ec_estimate": (None, [_I64, _I32, _P, _P, _P, _P]),
             "or_hilbert_index": (_I64, [_I32, _P]),
             "or_hilbert_positions": (ctypes.c_int, [_I32, _I64, _I64, _I64, _I64, _P, _P, _P]),
@@ -235,6 +237,28 @@ class Oracle:
                                  _ptr(dbar))
         if rc != 0:
             raise MemoryError("oracle adjoint could not allocate its tape")
+        return Ubar, dbar
+
+    def adjoint_run(self, mesh, fields, field_of_step, dt_of_step, nsub, x0, up0, d, lam):
+        """Reverse pass of a run whose step n takes nsub sub-steps of
+        dt_of_step[n] / nsub with field fields[field_of_step[n]].  Returns
+        (dL/d fields [nfields, 3, nz, ny, nx], dL/dd)."""
+        F = np.ascontiguousarray(fields, dtype=np.float64).reshape((-1,) + mesh.field_shape)
+        fs = np.ascontiguousarray(field_of_step, dtype=np.int32).reshape(-1)
+        dts = np.ascontiguousarray(dt_of_step, dtype=np.float64).reshape(-1)
+        assert fs.shape == dts.shape
+        x0 = _f64(x0, (-1, 3))
+        up0 = _f64(up0, (-1, 3))
+        d = _f64(d, (-1,))
+        lam = _f64(lam, mesh.field_shape)
+        Ubar = np.zeros(F.shape, dtype=np.float64)
+        dbar = np.zeros(d.shape[0], dtype=np.float64)
+        m = mesh.to_c()
+        rc = self.lib.or_adjoint_run(ctypes.byref(m), F.shape[0], _ptr(F), fs.shape[0], _ptr(fs),
+                                     _ptr(dts), int(nsub), x0.shape[0], _ptr(x0), _ptr(up0),
+                                     _ptr(d), _ptr(lam), _ptr(Ubar), _ptr(dbar))
+        if rc != 0:
+            raise ValueError("oracle adjoint rejected its arguments or could not allocate")
         return Ubar, dbar
 
 

@@ -258,26 +258,37 @@ void or_ec_estimate(int64_t n, int32_t kind, const double *S_last, double *S_pre
     }
 }
 
-int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
-               const double *x0, const double *up0, const double *d,
-               double dt, int32_t nsteps, const double *lambda, double *Ubar,
-               double *dbar)
+int or_adjoint_run(const or_mesh *m, int32_t nfields, const double *fields,
+                   int32_t nsteps, const int32_t *field_of_step,
+                   const double *dt_of_step, int32_t nsub, int64_t np,
+                   const double *x0, const double *up0, const double *d,
+                   const double *lambda, double *Ubar, double *dbar)
 {
-    /* Forward pass, keeping the state at the start of every step. */
+    if (nfields < 1 || nsteps < 0 || nsub < 1 || np < 0) return -1;
+    for (int32_t n = 0; n < nsteps; ++n)
+        if (field_of_step[n] < 0 || field_of_step[n] >= nfields || !(dt_of_step[n] > 0.0))
+            return -1;
+    int64_t nc = n_cells(m);
+    /* Forward pass, keeping the state at the start of every sub-step: the
+     * step n is nsub sub-steps of dt_n / nsub with its field held fixed. */
+    int64_t nss = (int64_t)nsteps * nsub;
     size_t per = (size_t)np * 3;
-    double *xs = (double *)malloc(sizeof(double) * per * (nsteps + 1));
-    double *us = (double *)malloc(sizeof(double) * per * (nsteps + 1));
-    double *scratch = (double *)calloc((size_t)3 * n_cells(m), sizeof(double));
+    double *xs = (double *)malloc(sizeof(double) * per * (size_t)(nss + 1));
+    double *us = (double *)malloc(sizeof(double) * per * (size_t)(nss + 1));
+    double *scratch = (double *)calloc((size_t)3 * nc, sizeof(double));
     if (!xs || !us || !scratch) {
         free(xs); free(us); free(scratch);
         return -1;
     }
     memcpy(xs, x0, sizeof(double) * per);
     memcpy(us, up0, sizeof(double) * per);
-    for (int32_t n = 0; n < nsteps; ++n) {
-        memcpy(xs + per * (n + 1), xs + per * n, sizeof(double) * per);
-        memcpy(us + per * (n + 1), us + per * n, sizeof(double) * per);
-        or_step(m, Uf, np, xs + per * (n + 1), us + per * (n + 1), d, dt, 1,
+    for (int64_t k = 0; k < nss; ++k) {
+        int32_t n = (int32_t)(k / nsub);
+        const double *Uf = fields + (size_t)field_of_step[n] * 3 * nc;
+        double dts = dt_of_step[n] / nsub;
+        memcpy(xs + per * (k + 1), xs + per * k, sizeof(double) * per);
+        memcpy(us + per * (k + 1), us + per * k, sizeof(double) * per);
+        or_step(m, Uf, np, xs + per * (k + 1), us + per * (k + 1), d, dts, 1,
                 scratch);
     }
 
@@ -286,10 +297,16 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
         double xbar[3] = {0, 0, 0}, ubar[3] = {0, 0, 0}, db = 0.0;
         double tau_s = or_tau(m, d[p]);
         double mass = or_mass(m, d[p]);
-        for (int32_t n = nsteps - 1; n >= 0; --n) {
-            const double *x = xs + per * n + 3 * p;
-            const double *up = us + per * n + 3 * p;
-            /* Recompute the forward quantities of this step. */
+        /* Sub-steps newest first; each reads the field of its step and adds
+         * that field's gradient. */
+        for (int64_t k = nss - 1; k >= 0; --k) {
+            int32_t n = (int32_t)(k / nsub);
+            const double *Uf = fields + (size_t)field_of_step[n] * 3 * nc;
+            double *Ub = Ubar + (size_t)field_of_step[n] * 3 * nc;
+            double dt = dt_of_step[n] / nsub;
+            const double *x = xs + per * k + 3 * p;
+            const double *up = us + per * k + 3 * p;
+            /* Recompute the forward quantities of this sub-step. */
             int32_t c0[3];
             or_cell(m, x, c0);
             stencil st;
@@ -336,17 +353,18 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
                     }
                 }
             }
-            /* Interpolation: u_f(x) = sum_k w_k(x) U[k]. */
-            for (int k = 0; k < 8; ++k) {
+            /* Interpolation: u_f(x) = sum_k w_k(x) U[k] (nearest grid point:
+             * one corner of weight 1, whose weight does not depend on x). */
+            for (int k8 = 0; k8 < 8; ++k8) {
                 double dot = 0.0;
                 for (int c = 0; c < 3; ++c) {
-                    int64_t q = field_index(m, c, st.cell[k][0], st.cell[k][1],
-                                            st.cell[k][2]);
-                    Ubar[q] += st.w[k] * ufbar[c];
+                    int64_t q = field_index(m, c, st.cell[k8][0], st.cell[k8][1],
+                                            st.cell[k8][2]);
+                    Ub[q] += st.w[k8] * ufbar[c];
                     dot += Uf[q] * ufbar[c];
                 }
                 if (m->interp != 1)
-                    for (int a = 0; a < 3; ++a) xbar[a] += st.dw[k][a] * dot;
+                    for (int a = 0; a < 3; ++a) xbar[a] += st.dw[k8][a] * dot;
             }
             /* tau = rho_p d^2/(18 mu): dtau/dd = 2 tau/d;
              * m = w rho_p pi d^3/6:   dm/dd = 3 m/d. */
@@ -359,6 +377,26 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
     free(us);
     free(scratch);
     return 0;
+}
+
+int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
+               const double *x0, const double *up0, const double *d,
+               double dt, int32_t nsteps, const double *lambda, double *Ubar,
+               double *dbar)
+{
+    /* One field and one sub-step per step: the general reverse pass. */
+    int32_t *fs = (int32_t *)calloc((size_t)(nsteps > 0 ? nsteps : 1), sizeof(int32_t));
+    double *dts = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1));
+    if (!fs || !dts) {
+        free(fs); free(dts);
+        return -1;
+    }
+    for (int32_t n = 0; n < nsteps; ++n) dts[n] = dt;
+    int r = or_adjoint_run(m, 1, Uf, nsteps, fs, dts, 1, np, x0, up0, d, lambda,
+                           Ubar, dbar);
+    free(fs);
+    free(dts);
+    return r;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -145,11 +145,27 @@ int or_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_begin, int64_t
 void or_bounding_boxes(int64_t np, const double *x, const int64_t *id, int64_t id0,
                        int64_t per_part, int64_t nparts, double *box);
 
-/* Reverse-mode derivative of nsteps single-sub-step calls of or_step
- * starting from (x0, up0), for a loss whose derivative with respect to the
- * time-integrated source Su_int is lambda ([3][n2][n1][n0]).  Adds dL/dUf to
- * Ubar ([3][n2][n1][n0]) and writes dL/dd to dbar ([np]).  Returns 0, or -1
- * if the forward tape could not be allocated. */
+/* Reverse-mode derivative of a run of or_step calls starting from (x0, up0),
+ * for a loss whose derivative with respect to the time-integrated source
+ * Su_int is lambda ([3][n2][n1][n0]).  The paper defines no adjoint: this is
+ * the derivative of the discrete step above, taken by reversing its
+ * operations (the deposit's transpose is a gather of lambda in the
+ * start-of-sub-step cell, the interpolation's transpose a scatter onto the
+ * field; the cell index and the periodic wrap are piecewise constant and
+ * contribute nothing).  Step n (0 <= n < nsteps) is nsub sub-steps of
+ * dt_of_step[n] / nsub with the field fields[field_of_step[n]] held fixed
+ * (fields: [nfields][3][n2][n1][n0]).  Adds dL/d(field k) to
+ * Ubar[k] ([nfields][3][n2][n1][n0]) and writes dL/dd to dbar ([np]).
+ * Returns 0, or -1 on bad arguments or if the forward tape could not be
+ * allocated. */
+int or_adjoint_run(const or_mesh *m, int32_t nfields, const double *fields,
+                   int32_t nsteps, const int32_t *field_of_step,
+                   const double *dt_of_step, int32_t nsub, int64_t np,
+                   const double *x0, const double *up0, const double *d,
+                   const double *lambda, double *Ubar, double *dbar);
+
+/* or_adjoint_run with one field and one sub-step of dt per step (nsteps
+ * calls of or_step with nsub = 1). */
 int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
                const double *x0, const double *up0, const double *d,
                double dt, int32_t nsteps, const double *lambda, double *Ubar,

@@ -475,6 +475,105 @@ def _adjoint_fd(orc, drag):
     assert checked >= 20, "too few field FD samples"
 
 
+def _general_loss_and_cells(orc, mesh, fields, fs, dts, nsub, x0, up0, d, T):
+    """Forward oracle run, sub-step by sub-step: step n is nsub sub-steps of
+    dts[n] / nsub with fields[fs[n]]; returns the loss against T, the source
+    and the cells at the start of every sub-step."""
+    x, up, S = x0, up0, None
+    cells = []
+    for n in range(len(fs)):
+        for _ in range(nsub):
+            cells.append(orc.cells(mesh, x))
+            x, up, S = orc.run(mesh, fields[fs[n]], x, up, d, dts[n] / nsub, 1, Su_int=S)
+    return float(np.sum((S - T) ** 2)), S, np.stack(cells)
+
+
+def _adjoint_fd_general(orc, drag, interp, nsub, nfields, fs, dts):
+    # central differences of the forward oracle against the reverse pass over
+    # sub-steps and per-step fields (the paper gives no adjoint; its
+    # sub-steps are Sec. 3.3, its nearest-grid-point gather Sec. 2.5)
+    mesh, U, x0, up0, d = _adjoint_case(drag)
+    mesh.interp = interp
+    rng = np.random.default_rng(22 + 7 * nsub + nfields + 3 * interp + 5 * drag)
+    fields = [U] + [_tg_field(mesh, rng, noise=0.3) for _ in range(nfields - 1)]
+    _, S, _ = _general_loss_and_cells(orc, mesh, fields, fs, dts, nsub, x0, up0, d, 0.0)
+    T = S * (1.0 + 0.3 * rng.normal(size=S.shape))
+    L0, S, cells = _general_loss_and_cells(orc, mesh, fields, fs, dts, nsub, x0, up0, d, T)
+    lam = 2.0 * (S - T)
+    Ubar, dbar = orc.adjoint_run(mesh, np.stack(fields), fs, dts, nsub, x0, up0, d, lam)
+    checked = 0
+    for p in range(d.shape[0]):
+        h = 1e-4 * d[p]
+        dp, dm = d.copy(), d.copy()
+        dp[p] += h
+        dm[p] -= h
+        Lp, _, cp = _general_loss_and_cells(orc, mesh, fields, fs, dts, nsub, x0, up0, dp, T)
+        Lm, _, cm = _general_loss_and_cells(orc, mesh, fields, fs, dts, nsub, x0, up0, dm, T)
+        if not (np.array_equal(cp, cells) and np.array_equal(cm, cells)):
+            continue
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - dbar[p]) <= 1e-5 * abs(fd) + 1e-9 * np.abs(dbar).max(), \
+            f"dL/dd particle {p}: fd {fd} adjoint {dbar[p]}"
+        checked += 1
+    assert checked >= 4, "too few diameter FD samples"
+    # the largest entries of every field's gradient
+    for k in range(nfields):
+        flat = np.argsort(-np.abs(Ubar[k]).ravel())[:10]
+        nk = 0
+        for q in flat:
+            idx = np.unravel_index(q, Ubar[k].shape)
+            h = 1e-4
+            Fp = [f.copy() for f in fields]
+            Fm = [f.copy() for f in fields]
+            Fp[k][idx] += h
+            Fm[k][idx] -= h
+            Lp, _, cp = _general_loss_and_cells(orc, mesh, Fp, fs, dts, nsub, x0, up0, d, T)
+            Lm, _, cm = _general_loss_and_cells(orc, mesh, Fm, fs, dts, nsub, x0, up0, d, T)
+            if not (np.array_equal(cp, cells) and np.array_equal(cm, cells)):
+                continue
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - Ubar[k][idx]) <= 1e-5 * abs(fd) + 1e-9 * np.abs(Ubar).max(), \
+                f"dL/dU field {k} {idx}: fd {fd} adjoint {Ubar[k][idx]}"
+            nk += 1
+        assert nk >= 8, f"too few FD samples of field {k}"
+    return Ubar, dbar
+
+
+def pin_adjoint_fd_substeps(orc):
+    # Stokes, trilinear, three sub-steps per step, one field
+    _adjoint_fd_general(orc, 0, 0, 3, 1, [0, 0, 0, 0], [2e-4] * 4)
+
+
+def pin_adjoint_fd_fields(orc):
+    # Schiller-Naumann, trilinear, a different field and length per step
+    _adjoint_fd_general(orc, 1, 0, 1, 3, [0, 1, 2, 1, 0, 2],
+                        [2e-4, 1e-4, 3e-4, 2e-4, 1.5e-4, 2.5e-4])
+
+
+def pin_adjoint_fd_ngp(orc):
+    # Stokes, nearest grid point, two sub-steps, two fields
+    _adjoint_fd_general(orc, 0, 1, 2, 2, [0, 1, 1, 0, 1], [2e-4, 3e-4, 1e-4, 2e-4, 2e-4])
+
+
+def pin_adjoint_fd_ngp_sn(orc):
+    # Schiller-Naumann, nearest grid point, one field
+    _adjoint_fd_general(orc, 1, 1, 1, 1, [0] * 6, [2e-4] * 6)
+
+
+def pin_adjoint_special_case(orc):
+    # one field, one sub-step of a fixed length: the general reverse pass and
+    # the single-field one are the same computation; three distinct fields
+    # that are equal give gradients summing to the single-field one
+    mesh, U, x0, up0, d = _adjoint_case(0)
+    rng = np.random.default_rng(23)
+    lam = rng.normal(size=U.shape)
+    Ub1, db1 = orc.adjoint(mesh, U, x0, up0, d, 2e-4, 6, lam)
+    Ub3, db3 = orc.adjoint_run(mesh, np.stack([U, U, U]), [0, 1, 2, 0, 1, 2], [2e-4] * 6, 1,
+                               x0, up0, d, lam)
+    assert np.array_equal(db1, db3), "dL/dd independent of how the equal fields are named"
+    assert np.allclose(Ub3.sum(axis=0), Ub1, rtol=0, atol=1e-13 * np.abs(Ub1).max())
+
+
 # ---------------------------------------------------------------------------
 # extrapolator-corrector (paper Sec. 2.4) and two-way coupling (Sec. 3.1)
 # ---------------------------------------------------------------------------
@@ -648,7 +747,9 @@ ALL_PINS = [
     pin_cell_brute_force, pin_wrap, pin_interp_cell_centre, pin_interp_affine,
     pin_interp_shift, pin_interp_ngp, pin_interp_transpose, pin_closed_form_uniform,
     pin_terminal_velocity, pin_first_order, pin_conservation, pin_start_cell_deposit,
-    pin_rotating_field, pin_adjoint_fd, pin_adjoint_fd_sn, pin_sn_terminal_velocity,
+    pin_rotating_field, pin_adjoint_fd, pin_adjoint_fd_sn, pin_adjoint_fd_substeps,
+    pin_adjoint_fd_fields, pin_adjoint_fd_ngp, pin_adjoint_fd_ngp_sn, pin_adjoint_special_case,
+    pin_sn_terminal_velocity,
     pin_sn_force, pin_ec_conservative, pin_ec_exact_histories,
     pin_two_way_relaxation, pin_hilbert_curve, pin_hilbert_segments, pin_bounding_boxes,
 ]

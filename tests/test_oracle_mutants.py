@@ -66,7 +66,7 @@ MUTANTS = {
         ("wbar[a] = ubar[a] + dt * xbar[a] + mass * Jbar[a];",
          "wbar[a] = ubar[a] + mass * Jbar[a];"),
     "adjoint: interpolation-gradient term dropped":
-        ("for (int a = 0; a < 3; ++a) xbar[a] += st.dw[k][a] * dot;", ";"),
+        ("for (int a = 0; a < 3; ++a) xbar[a] += st.dw[k8][a] * dot;", ";"),
     "adjoint: response-time cotangent sign":
         ("taubar += wbar[a] * (up[a] + dt * m->g[a] - up_new[a]) / D;",
          "taubar -= wbar[a] * (up[a] + dt * m->g[a] - up_new[a]) / D;"),
@@ -85,6 +85,20 @@ MUTANTS = {
         ("mbar * 3.0 * mass / d[p]", "mbar * 2.0 * mass / d[p]"),
     "adjoint: dtau/dd factor":
         ("tausbar * 2.0 * tau_s / d[p]", "tausbar * tau_s / d[p]"),
+    "adjoint: sub-step length not divided":
+        ("double dt = dt_of_step[n] / nsub;", "double dt = dt_of_step[n];"),
+    "adjoint: every sub-step reversed from the state at its step's start":
+        ("const double *x = xs + per * k + 3 * p;",
+         "const double *x = xs + per * (k - k % nsub) + 3 * p;"),
+    "adjoint: every step read with the first step's field":
+        ("const double *Uf = fields + (size_t)field_of_step[n] * 3 * nc;\n            double *Ub",
+         "const double *Uf = fields;\n            double *Ub"),
+    "adjoint: every field's gradient added to the first field":
+        ("double *Ub = Ubar + (size_t)field_of_step[n] * 3 * nc;", "double *Ub = Ubar;"),
+    "adjoint: trilinear stencil in the reverse of nearest-grid-point steps":
+        ("            stencil st;\n            make_stencil(m, x, &st);\n            double ufp[3], up_new[3];",
+         "            stencil st;\n            { or_mesh tm = *m; tm.interp = 0; make_stencil(&tm, x, &st); }\n"
+         "            double ufp[3], up_new[3];"),
     "Schiller-Naumann exponent":
         ("0.15 * pow(slip_reynolds(m, d, slip), 0.687)", "0.15 * pow(slip_reynolds(m, d, slip), 0.786)"),
     "Schiller-Naumann coefficient":
