@@ -96,19 +96,28 @@ typedef struct {
     int64_t capacity;      /* maximum number of particles, >= 1 */
 } st_mesh_desc;
 
-/* Creates a context on HIP device `device` and allocates, once, every
+/* Paper Sec. 2.5 (the Lagrangian solver needs the domain geometry, the mesh
+ * and the Eulerian fields) and Sec. 2.2 (particles held as structure of
+ * arrays per partition; here the partitions are fixed 8^3-cell chunks).
+ * Creates a context on HIP device `device` and allocates, once, every
  * buffer a run of up to desc->capacity particles needs.  *out receives the
  * context.  ST_ERR_INVALID for a bad descriptor, ST_ERR_OOM when the device
  * cannot hold the buffers. */
 st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out);
 
-/* Frees every buffer of the context (after synchronising its device). */
+/* Outside the paper (lifetime of a context).
+ * Frees every buffer of the context (after synchronising its device). */
 st_status st_destroy(st_ctx *ctx);
 
-/* Message describing the last error of this context ("" if none). */
+/* Outside the paper (error reporting).
+ * Message describing the last error of this context ("" if none);
+ * st_last_error(NULL) describes the last failed st_create_mesh of the
+ * calling thread. */
 const char *st_last_error(const st_ctx *ctx);
 
-/* Adds n particles: x, up [n][3] (positions in [0,L) per axis, velocities),
+/* Paper Sec. 2.3 (particles are created directly on the GPU) and Sec. 3.2
+ * (parcels: each represents parcel_weight droplets).
+ * Adds n particles: x, up [n][3] (positions in [0,L) per axis, velocities),
  * d [n] (diameters > 0), all binary64.  Positions outside the box are
  * wrapped periodically.  New ids continue the injection order.  Host
  * arrays are validated on the host (non-finite values or d <= 0 give
@@ -118,10 +127,13 @@ const char *st_last_error(const st_ctx *ctx);
 st_status st_inject(st_ctx *ctx, int64_t n, const double *x, const double *up,
                     const double *d, int on_device, void *hip_stream);
 
-/* Number of particles in the context. */
+/* Outside the paper (bookkeeping).  Number of particles in the context. */
 st_status st_count(const st_ctx *ctx, int64_t *n);
 
-/* Advances every particle by dt with nsub sub-steps of dt/nsub, the field
+/* Paper Sec. 2.1 (equation of motion, drag, momentum source), Sec. 2.5
+ * (semi-implicit Euler, interpolation and deposit in the containing cell)
+ * and Sec. 3.3 (sub-steps); the steps numbered in the header above.
+ * Advances every particle by dt with nsub sub-steps of dt/nsub, the field
  * u_cells (device memory, [3][n2][n1][n0], binary64 for ST_FORM_FP64 and
  * binary32 otherwise) held fixed (paper Sec. 3.3, sub-steps).  Each
  * sub-step adds its deposit to the context's time-integrated source.
@@ -132,14 +144,18 @@ st_status st_count(const st_ctx *ctx, int64_t *n);
 st_status st_step(st_ctx *ctx, const void *u_cells, double dt, int32_t nsub,
                   int32_t tape, void *hip_stream);
 
-/* Copies the time-integrated momentum source, sum over sub-steps of
+/* Paper Sec. 2.1 (momentum source S_u) and Sec. 2.5 (the sources are fed
+ * back to the Eulerian solver).
+ * Copies the time-integrated momentum source, sum over sub-steps of
  * S_u dt [kg/(m^2 s)] = -(sum of impulses J) / V_cell per cell, as binary64
  * [3][n2][n1][n0] into out.  reset != 0 zeroes the context's accumulator
  * afterwards. */
 st_status st_get_sources(st_ctx *ctx, double *out, int32_t reset,
                          int on_device, void *hip_stream);
 
-/* Copies the particle state, indexed by id, into any of the non-NULL
+/* Outside the paper (read-out of the state for checks and output; the
+ * paper's particle state is position, velocity and diameter, Sec. 2.1).
+ * Copies the particle state, indexed by id, into any of the non-NULL
  * outputs: x, up [count][3] binary64 (positions in [0,L)), d [count]
  * binary64, id [count] int64 (id[i] = i once the copy is complete, a
  * check of the permutation), cell [count][3] int32 (cell per axis). */
@@ -147,7 +163,16 @@ st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
                            int64_t *id, int32_t *cell, int on_device,
                            void *hip_stream);
 
-/* Reverse-mode derivative of the taped steps.  dL_dSint (device,
+/* Outside the paper: the paper defines no adjoint.  This is the derivative
+ * of the discrete step st_step computes (Sec. 2.1, Sec. 2.5), taken by
+ * reversing its operations: the deposit's transpose is a gather of
+ * dL/dS_int in the start-of-step cell, the interpolation's transpose a
+ * scatter onto the field; the cell index and the periodic wrap are
+ * piecewise constant and contribute nothing.  The differentiable form and
+ * its checkpointing (every `tape` sub-steps, recomputation in between)
+ * follow the workload's definition of differentiation with respect to the
+ * fluid velocity field and the particle diameters.
+ * Reverse-mode derivative of the taped steps.  dL_dSint (device,
  * [3][n2][n1][n0] binary64) is the derivative of a scalar loss with respect
  * to the time-integrated source accumulated by the taped steps.  Writes
  * dL/du (device, [3][n2][n1][n0] binary64; the sum over the taped steps'
@@ -159,10 +184,14 @@ st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
 st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,
                       double *dL_dd, void *hip_stream);
 
-/* Drops the tape without differentiating. */
+/* Outside the paper (see st_backward).  Drops the tape without
+ * differentiating. */
 st_status st_tape_clear(st_ctx *ctx);
 
-/* Asynchronously coupled run (paper Sec. 2.3, at most one step of lag):
+/* Paper Sec. 2.3 (asynchronous coupling; the Eulerian and Lagrangian phases
+ * at most one time step apart) and Sec. 2.5 (the lag of one step).  On one
+ * GPU the Eulerian update is a synthetic field rotation on a second stream.
+ * Asynchronously coupled run:
  * nsteps steps of dt in which step k uses the field
  * U^k = R_z(theta_k) U^0, rotated about z with (cos, sin) of theta_k given
  * in cs[2k], cs[2k+1] (host memory).  A second stream owned by the context
@@ -184,8 +213,13 @@ typedef enum {
     ST_EXTRAP_LINEAR = 2   /* linear extrapolation from the last two sources */
 } st_extrapolator;
 
-/* Extrapolator-corrector for a fluid solver that runs one step ahead of the
- * particles (paper Sec. 2.4, the estimated source of the current step).  At
+/* Paper Sec. 2.4 (extrapolator-corrector method: corrector, estimated
+ * source, zero, constant and linear extrapolators).  The corrector subtracts
+ * the previous extrapolation (the part of the previous estimate that stood
+ * in for the then unknown source), which makes the applied sources add up
+ * to the actual ones (the conservation over time the section states).
+ * Extrapolator-corrector for a fluid solver that runs one step ahead of the
+ * particles.  At
  * the current step only S_last, the actual time-integrated source of the
  * previous step (e.g. from st_get_sources with reset), is available.  Per
  * cell and component the call returns in `applied`
@@ -200,17 +234,21 @@ typedef enum {
 st_status st_ec_estimate(st_ctx *ctx, int32_t kind, const double *S_last, double *applied,
                          int on_device, void *hip_stream);
 
-/* Clears the extrapolator-corrector's history (E_prev = S_prev = 0). */
+/* Paper Sec. 2.4 (no source is available before the first step).  Clears
+ * the extrapolator-corrector's history (E_prev = S_prev = 0). */
 st_status st_ec_reset(st_ctx *ctx, void *hip_stream);
 
-/* Counters of the last st_step (host memory): movers, full repacks so far,
+/* Outside the paper (instrumentation of the re-bin).
+ * Counters of the last st_step (host memory): movers, full repacks so far,
  * particles, store slots, work items (chunk runs of the step kernel).  Any
  * pointer may be NULL.  Synchronises the stream. */
 st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
                    int64_t *particles, int64_t *slots, int64_t *items,
                    void *hip_stream);
 
-/* Device time of the step kernel (the per-particle gather, integrate,
+/* Outside the paper (measurement; the paper reports times per step,
+ * Sec. 4).
+ * Device time of the step kernel (the per-particle gather, integrate,
  * deposit and relocate) measured with a pair of HIP events attached to each
  * of its launches (hipExtLaunchKernel), which take the start and end of the
  * kernel's own execution on the launch stream.  enable != 0 starts a measurement (clearing
@@ -220,8 +258,9 @@ st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
 st_status st_timing(st_ctx *ctx, int32_t enable, double *kernel_ms,
                     int64_t *launches);
 
-/* Positions of new particles placed by Hilbert-curve segments (paper
- * Sec. 2.2, initialisation).  The domain [0,L) is a lattice of 2^order voxels
+/* Paper Sec. 2.2 (particles initialised along a Hilbert curve whose
+ * segments give the initial partitions).
+ * Positions of new particles placed by Hilbert-curve segments.  The domain [0,L) is a lattice of 2^order voxels
  * per axis (order 1..10) visited in Hilbert-curve order (the orientation of
  * Skilling's transpose algorithm, AIP Conf. Proc. 707, 2004: the curve starts
  * in voxel (0,0,0) and ends in (2^order - 1, 0, 0)); its V = 8^order voxels are
@@ -236,7 +275,9 @@ st_status st_hilbert_positions(st_ctx *ctx, int32_t order, int64_t nseg, int64_t
                                int64_t seg_end, int64_t per_seg, const double *u, double *x,
                                int32_t on_device, void *hip_stream);
 
-/* Injects the particles that st_hilbert_positions places, with velocities up
+/* Paper Sec. 2.2 (initialisation by Hilbert segments) and Sec. 2.3
+ * (particles created on the GPU).
+ * Injects the particles that st_hilbert_positions places, with velocities up
  * ([n][3]) and diameters d ([n]); their ids continue the injection order, so
  * particle k of segment s gets id first + (s - seg_begin) per_seg + k.  Any
  * range of segments can be injected independently (the placement is global
@@ -246,8 +287,10 @@ st_status st_inject_hilbert(st_ctx *ctx, int32_t order, int64_t nseg, int64_t se
                             int64_t seg_end, int64_t per_seg, const double *u, const double *up,
                             const double *d, int32_t on_device, void *hip_stream);
 
-/* Axis-aligned bounding boxes of particle partitions (paper Sec. 2.2, chunk
- * bounding boxes): partition p (0 <= p < nparts) holds the particles with id in
+/* Paper Sec. 2.2 (a rectangular box around the particles of each partition,
+ * which identifies the Eulerian partitions it needs) and Sec. 2.3 (the boxes
+ * are computed on the GPU and sent to the host).
+ * Axis-aligned bounding boxes of particle partitions: partition p (0 <= p < nparts) holds the particles with id in
  * [id0 + p per_part, id0 + (p+1) per_part).  boxes ([nparts][6] binary64:
  * min x, min y, min z, max x, max y, max z, over the positions st_get_particles
  * returns; device memory when on_device) receives them; an empty partition gets

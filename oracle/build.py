@@ -9,6 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "st_oracle.c")
+PAR = os.path.join(HERE, "st_oracle_par.c")
 LIB = os.path.join(HERE, "libst_oracle.so")
 
 # -ffp-contract=off: every multiply and add is rounded as written.
@@ -16,7 +17,8 @@ CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-Wall"]
 
 
 def build(src=SRC, out=LIB, extra=()):
-    cmd = ["gcc", *CFLAGS, *extra, src, "-o", out, "-lm"]
+    """The serial oracle plus its particle-parallel drivers (OpenMP)."""
+    cmd = ["gcc", *CFLAGS, "-fopenmp", *extra, src, PAR, "-o", out, "-lm"]
     subprocess.run(cmd, check=True)
     return out
 

@@ -83,6 +83,15 @@ def _f64(a, shape=None):
     return a
 
 
+def default_threads():
+    """Threads for the particle-parallel drivers: OMP_NUM_THREADS when set,
+    else the host's cores, at most 16 (a GPU machine's share of its host)."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return min(16, os.cpu_count() or 1)
+
+
 class Oracle:
     """Loaded oracle library; every method copies its inputs."""
 
@@ -105,6 +114,9 @@ class Oracle:
             "or_adjoint": (ctypes.c_int, [M, _P, _I64, _P, _P, _P, _D, _I32, _P, _P, _P]),
             "or_adjoint_run": (ctypes.c_int, [M, _I32, _P, _I32, _P, _P, _I32, _I64, _P, _P,
                                               _P, _P, _P, _P]),
+            "or_run_par": (ctypes.c_int, [M, _P, _I64, _P, _P, _P, _D, _I32, _I32, _P, _I32]),
+            "or_adjoint_run_par": (ctypes.c_int, [M, _I32, _P, _I32, _P, _P, _I32, _I64, _P,
+                                                  _P, _P, _P, _P, _P, _I32]),
             "or_ec_estimate": (None, [_I64, _I32, _P, _P, _P, _P]),
             "or_hilbert_index": (_I64, [_I32, _P]),
             "or_hilbert_positions": (ctypes.c_int, [_I32, _I64, _I64, _I64, _I64, _P, _P, _P]),
@@ -168,6 +180,25 @@ class Oracle:
         m = mesh.to_c()
         self.lib.or_run(ctypes.byref(m), _ptr(Uf), x.shape[0], _ptr(x), _ptr(up),
                         _ptr(d), float(dt), int(nsteps), int(nsub), _ptr(S))
+        return x, up, S
+
+    def run_par(self, mesh, Uf, x, up, d, dt, nsteps, nsub=1, Su_int=None, threads=None):
+        """run() with the particles split over `threads` threads (all cores by
+        default); the per-cell sums are added in a different order."""
+        threads = threads or default_threads()
+        Uf = _f64(Uf, mesh.field_shape)
+        x = _f64(x, (-1, 3)).copy()
+        up = _f64(up, (-1, 3)).copy()
+        d = _f64(d, (-1,))
+        assert x.shape == up.shape and d.shape[0] == x.shape[0]
+        S = (np.zeros(mesh.field_shape, dtype=np.float64) if Su_int is None
+             else _f64(Su_int, mesh.field_shape).copy())
+        m = mesh.to_c()
+        rc = self.lib.or_run_par(ctypes.byref(m), _ptr(Uf), x.shape[0], _ptr(x), _ptr(up),
+                                 _ptr(d), float(dt), int(nsteps), int(nsub), _ptr(S),
+                                 int(threads))
+        if rc != 0:
+            raise MemoryError("or_run_par could not allocate its per-thread sources")
         return x, up, S
 
     def run_rotating(self, mesh, U0, cs, x, up, d, dt, nsteps, Su_int=None):
@@ -257,6 +288,29 @@ class Oracle:
         rc = self.lib.or_adjoint_run(ctypes.byref(m), F.shape[0], _ptr(F), fs.shape[0], _ptr(fs),
                                      _ptr(dts), int(nsub), x0.shape[0], _ptr(x0), _ptr(up0),
                                      _ptr(d), _ptr(lam), _ptr(Ubar), _ptr(dbar))
+        if rc != 0:
+            raise ValueError("oracle adjoint rejected its arguments or could not allocate")
+        return Ubar, dbar
+
+    def adjoint_run_par(self, mesh, fields, field_of_step, dt_of_step, nsub, x0, up0, d, lam,
+                        threads=None):
+        """adjoint_run() with the particles split over `threads` threads."""
+        threads = threads or default_threads()
+        F = np.ascontiguousarray(fields, dtype=np.float64).reshape((-1,) + mesh.field_shape)
+        fs = np.ascontiguousarray(field_of_step, dtype=np.int32).reshape(-1)
+        dts = np.ascontiguousarray(dt_of_step, dtype=np.float64).reshape(-1)
+        assert fs.shape == dts.shape
+        x0 = _f64(x0, (-1, 3))
+        up0 = _f64(up0, (-1, 3))
+        d = _f64(d, (-1,))
+        lam = _f64(lam, mesh.field_shape)
+        Ubar = np.zeros(F.shape, dtype=np.float64)
+        dbar = np.zeros(d.shape[0], dtype=np.float64)
+        m = mesh.to_c()
+        rc = self.lib.or_adjoint_run_par(ctypes.byref(m), F.shape[0], _ptr(F), fs.shape[0],
+                                         _ptr(fs), _ptr(dts), int(nsub), x0.shape[0], _ptr(x0),
+                                         _ptr(up0), _ptr(d), _ptr(lam), _ptr(Ubar), _ptr(dbar),
+                                         int(threads))
         if rc != 0:
             raise ValueError("oracle adjoint rejected its arguments or could not allocate")
         return Ubar, dbar

@@ -171,6 +171,22 @@ int or_adjoint(const or_mesh *m, const double *Uf, int64_t np,
                double dt, int32_t nsteps, const double *lambda, double *Ubar,
                double *dbar);
 
+/* Particle-parallel drivers (st_oracle_par.c): the same computations as
+ * or_run and or_adjoint_run, with the particles split into nthreads
+ * contiguous ranges run on their own threads and the per-range source or
+ * gradient arrays added in range order.  Particle states and dL/dd are
+ * bitwise those of the serial calls; per-cell sums differ only by the order
+ * of the additions.  Return 0, or -1 on bad arguments or allocation
+ * failure. */
+int or_run_par(const or_mesh *m, const double *Uf, int64_t np, double *x, double *up,
+               const double *d, double dt, int32_t nsteps, int32_t nsub, double *Su_int,
+               int32_t nthreads);
+int or_adjoint_run_par(const or_mesh *m, int32_t nfields, const double *fields,
+                       int32_t nsteps, const int32_t *field_of_step, const double *dt_of_step,
+                       int32_t nsub, int64_t np, const double *x0, const double *up0,
+                       const double *d, const double *lambda, double *Ubar, double *dbar,
+                       int32_t nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,3 +117,58 @@ def lockstep_check(t, orc, mesh, Udev, Uor, dt, nsteps, tol, nsub=1):
 
 def sphere_mass(d, w=1.0, rho_p=1000.0):
     return w * rho_p * math.pi * d ** 3 / 6.0
+
+
+def in_window(cell, lo, size, n, margin=0):
+    """Mask of cells (int [P, 3], torch or numpy) inside the periodic window of
+    cells [lo - margin, lo + size + margin) per axis."""
+    ok = None
+    for a in range(3):
+        r = (cell[:, a] - (lo[a] - margin)) % n[a]
+        m = r < size + 2 * margin
+        ok = m if ok is None else ok & m
+    return ok
+
+
+def window_index(lo, size, n):
+    """Index arrays (z, y, x) of the window's cells in a [nz, ny, nx] field."""
+    ax = [(np.arange(size) + lo[a]) % n[a] for a in range(3)]
+    return np.ix_(ax[2], ax[1], ax[0])
+
+
+def lockstep_window(t, orc, mesh, Udev, Uor, dt, lo, size, tol):
+    """One lockstep step checked per cell over a window of cells, at any size:
+    a cell's source comes only from the droplets whose cell at the start of
+    the step is that cell, so the oracle steps exactly the droplets that the
+    GPU holds in the window (their stored state promoted to binary64) and the
+    two sources must agree in every window cell to `tol` of the largest.
+    Returns (error, droplets in the window)."""
+    import torch
+    t.sources(reset=True)
+    s = t.particles()
+    sel = in_window(s["cell"], lo, size, mesh.n)
+    xs, us, ds = (s[k][sel].cpu().numpy() for k in ("x", "up", "d"))
+    del s, sel
+    torch.cuda.empty_cache()
+    t.step(Udev, dt)
+    S = t.sources(reset=True).cpu().numpy()
+    _, _, So = orc.run_par(mesh, Uor, xs, us, ds, dt, 1)
+    wi = window_index(lo, size, mesh.n)
+    err = 0.0
+    for c in range(3):
+        ref = So[c][wi]
+        scale = np.abs(ref).max()
+        if scale > 0:
+            err = max(err, float(np.abs(S[c][wi] - ref).max() / scale))
+    assert err <= tol, (err, tol, lo, size)
+    return err, xs.shape[0]
+
+
+def displacement_bound(w, U, up0_max, d_max, nsteps, dt):
+    """Largest distance [m] a droplet can travel in nsteps steps of dt (Stokes
+    drag): each velocity update is a convex combination of the old velocity
+    and u_f + tau g, so |u_p| never exceeds max(|u_p0|, max|u_f| + tau_max |g|)."""
+    tau_max = w.rho_p * d_max ** 2 / (18.0 * w.mu_f)
+    umax = float(np.sqrt((np.asarray(U) ** 2).sum(axis=0)).max())
+    vmax = max(up0_max, umax + tau_max * float(np.linalg.norm(w.g)))
+    return nsteps * dt * vmax

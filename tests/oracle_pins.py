@@ -657,6 +657,103 @@ def pin_two_way_relaxation(orc):
     assert errs[-1] < 1e-5, f"two-way relaxation error {errs[-1]}"
 
 
+def two_way_history(step, ec, mode, dt, t_end, m_ratio=1.0):
+    """The single-droplet two-way test of paper Sec. 3.1, driven by a step
+    function: a 100 um droplet at 1 m/s in a quiescent 0-D fluid of mass
+    m_p / m_ratio on a 2^3 periodic mesh of 1 mm.  step(uf) runs the particle
+    step with the uniform fluid velocity uf and returns the step's
+    time-integrated source [3*8]; the fluid takes sum(S) V / m_f, either the
+    step's own source (conventional coupling) or, one step ahead of the
+    particles, the extrapolator-corrector's estimate ec(kind, S_last) from
+    the previous step's source (asynchronous coupling, Sec. 2.4).  Returns
+    e_rel = |p_f,num - p_f,exact| / p_total at every step (Sec. 3.1) against
+    the exact two-body solution, whose relative velocity decays at
+    (1 + m_p/m_f)/tau."""
+    d = 100e-6
+    m_p = 1000.0 * math.pi * d ** 3 / 6.0
+    m_f = m_p / m_ratio
+    tau = _stokes_tau(d)
+    V = (1e-3 / 2) ** 3
+    uf = np.zeros(3)
+    S_prev = np.zeros(24)
+    nsteps = int(round(t_end / dt))
+    err = np.empty(nsteps)
+    for n in range(nsteps):
+        S = step(uf).ravel()
+        applied = S if mode == "conventional" else ec(mode, S_prev)
+        S_prev = S
+        uf = uf + applied.reshape(3, -1).sum(axis=1) * V / m_f
+        t = (n + 1) * dt
+        w = math.exp(-(1 + m_p / m_f) * t / tau)
+        exact = m_f * (m_p - m_p * w) / (m_p + m_f)
+        err[n] = abs(m_f * uf[0] - exact) / m_p
+    return err
+
+
+def two_way_mesh(m_ratio=1.0):
+    d, L = 100e-6, 1e-3
+    m_f = 1000.0 * math.pi * d ** 3 / 6.0 / m_ratio
+    return MeshParams(n=(2, 2, 2), L=(L, L, L), g=(0.0, 0.0, 0.0), rho_f=m_f / L ** 3,
+                      rho_p=1000.0, mu_f=MU_F)
+
+
+def ec_norms(err):
+    """L1 (mean) and L-infinity of e_rel without the first 10 % of the steps,
+    as Sec. 3.1 measures them."""
+    e = err[len(err) // 10:]
+    return float(e.mean()), float(e.max())
+
+
+def check_ec_convergence(norms):
+    """The paper's statements about the error norms (Sec. 3.1) on norms[mode]
+    = [(L1, Linf) per halving of dt]: every schedule converges at least at
+    first order in L1; no extrapolation gives higher errors and a lower
+    order in L-infinity than the conventional coupling; the constant
+    extrapolator behaves almost like the conventional coupling; the linear
+    one is the worst at the largest step and reaches the conventional level
+    as the step decreases."""
+    def order(vals):
+        return [math.log2(vals[i] / vals[i + 1]) for i in range(len(vals) - 1)]
+    l1 = {m: [v[0] for v in r] for m, r in norms.items()}
+    li = {m: [v[1] for v in r] for m, r in norms.items()}
+    for m in norms:
+        o = order(l1[m])[-3:]
+        assert min(o) > 0.9, f"{m}: L1 orders {o}"
+    assert np.mean(order(li["zero"])[-3:]) < np.mean(order(li["conventional"])[-3:]) - 0.5
+    assert l1["zero"][-1] > 10 * l1["conventional"][-1]
+    assert l1["const"][-1] < 10 * l1["conventional"][-1]
+    assert l1["linear"][0] == max(v[0] for v in l1.values())
+    assert l1["linear"][-1] < 2 * l1["conventional"][-1]
+
+
+def pin_ec_convergence(orc):
+    # dt halved from tau/4 to tau/128 over four response times
+    tau = _stokes_tau(100e-6)
+    mesh = two_way_mesh()
+    norms = {}
+    for mode in ("conventional", "zero", "const", "linear"):
+        norms[mode] = []
+        for k in (4, 8, 16, 32, 64, 128):
+            dt = tau / k
+            st = {"x": np.array([[0.3e-3, 0.4e-3, 0.5e-3]]), "up": np.array([[1.0, 0.0, 0.0]])}
+            ec_state = {"S_prev2": np.zeros(24), "ext_prev": np.zeros(24)}
+
+            def step(uf, st=st, dt=dt):
+                U = np.empty(mesh.field_shape)
+                for c in range(3):
+                    U[c] = uf[c]
+                st["x"], st["up"], S = orc.run(mesh, U, st["x"], st["up"], np.array([100e-6]),
+                                               dt, 1)
+                return S
+
+            def ec(kind, S_last, ec_state=ec_state):
+                return orc.ec_estimate({"zero": 0, "const": 1, "linear": 2}[kind], S_last,
+                                       ec_state)
+
+            norms[mode].append(ec_norms(two_way_history(step, ec, mode, dt, 4 * tau)))
+    check_ec_convergence(norms)
+
+
 # ---------------------------------------------------------------------------
 # Hilbert segments and bounding boxes (paper Sec. 2.2)
 # ---------------------------------------------------------------------------
@@ -751,7 +848,7 @@ ALL_PINS = [
     pin_adjoint_fd_fields, pin_adjoint_fd_ngp, pin_adjoint_fd_ngp_sn, pin_adjoint_special_case,
     pin_sn_terminal_velocity,
     pin_sn_force, pin_ec_conservative, pin_ec_exact_histories,
-    pin_two_way_relaxation, pin_hilbert_curve, pin_hilbert_segments, pin_bounding_boxes,
+    pin_two_way_relaxation, pin_ec_convergence, pin_hilbert_curve, pin_hilbert_segments, pin_bounding_boxes,
 ]
 
 

@@ -3,10 +3,13 @@ finite differences of the GPU forward run.
 
 Loss: L = sum (S_int - T)^2 over the time-integrated source, T built from a
 run with the diameters scaled by 1.1; so dL/dS_int = 2 (S_int - T).
-Gradients are compared in relative L2 norm, 1e-4 for the FP32 chunk-local
-form (forward in binary32, adjoint in binary64) and near round-off for the
-FP64 form; FD samples whose per-step cells change between the +h and -h
-runs are excluded and counted.
+Gradients are compared with the oracle's in relative L2 norm and entry by
+entry: the largest entry difference over the largest reference entry, and
+the relative difference of every entry above a floor of 1e-3 of the largest.
+The bounds are 1e-4 (norm and largest entry) for the FP32 chunk-local form
+(forward in binary32, adjoint in binary64) and near round-off for the FP64
+form; FD samples whose per-step cells change between the +h and -h runs are
+excluded and counted.
 """
 import numpy as np
 import pytest
@@ -41,6 +44,80 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+# entry-by-entry bounds: (largest difference / largest entry, relative
+# difference of entries above 1e-3 of the largest)
+ENTRY_TOL = {"fp64": (1e-9, 1e-7), "fp32_local": (1e-4, 1e-2)}
+
+
+def _entrywise(g, ref, form, what):
+    """Asserts the entry-by-entry bounds of the form; returns the two errors."""
+    scale = np.abs(ref).max()
+    emax = float(np.abs(g - ref).max() / scale)
+    big = np.abs(ref) > 1e-3 * scale
+    erel = float((np.abs(g - ref)[big] / np.abs(ref)[big]).max())
+    print(f"{form} {what}: largest-entry error {emax:.3e}, worst relative error above the "
+          f"floor {erel:.3e} over {int(big.sum())} entries")
+    tmax, trel = ENTRY_TOL[form]
+    assert emax <= tmax, (what, emax)
+    assert erel <= trel, (what, erel)
+    return emax, erel
+
+
+def _far_from_faces(orc, mesh, Uor, fs, dts, nsub, x0, up0, d, band=1e-4):
+    """Droplets whose oracle trajectory never starts a sub-step within `band`
+    cell widths of a face (only those can deposit into another cell in a
+    binary32 forward)."""
+    h = mesh.h
+    near = np.zeros(x0.shape[0], dtype=bool)
+    x, u = x0, up0
+    for k, dt in zip(fs, dts):
+        for _ in range(nsub):
+            q = x / h
+            f = q - np.floor(q)
+            near |= (np.minimum(f, 1.0 - f) < band).any(axis=1)
+            x, u, _ = orc.run_par(mesh, Uor[k], x, u, d, dt / nsub, 1)
+    return ~near
+
+
+def _entrywise_far(orc, w, form, mesh, Ud, Uor, fs, dts, nsub, s0, lam, K,
+                   drag="stokes", interp="trilinear", dd_full=None):
+    """Entry-by-entry comparison for a binary32 forward.  The gradient for a
+    given dL/dS_int is a sum over droplets, so the droplets that stay away
+    from the faces are run again on their own (from the stored initial state,
+    which re-injection reproduces exactly) and their adjoint is compared with
+    the oracle's reverse pass over the same droplets, entry by entry; the
+    droplets left out are counted."""
+    import torch
+    keep = _far_from_faces(orc, mesh, Uor, fs, dts, nsub, s0["x"], s0["up"], s0["d"])
+    n = int(keep.sum())
+    t = tracker(w, form, capacity=n, drag=drag, interp=interp)
+    t.inject(s0["x"][keep], s0["up"][keep], s0["d"][keep])
+    for k, dt in zip(fs, dts):
+        t.step(Ud[k], dt, nsub=nsub, tape=K)
+    dU, dd = (g.cpu().numpy() for g in t.backward(torch.from_numpy(lam).cuda()))
+    t.close()
+    oU, od = orc.adjoint_run_par(mesh, np.stack(Uor), fs, dts, nsub, s0["x"][keep],
+                                 s0["up"][keep], s0["d"][keep], lam)
+    print(f"per entry on the {n} of {keep.size} droplets away from the faces:")
+    _entrywise(dU, oU.sum(axis=0), form, "dL/du")
+    _entrywise(dd, od, form, "dL/dd")
+    if dd_full is not None:
+        # a droplet's dL/dd does not depend on the other droplets
+        assert np.array_equal(dd, dd_full[keep])
+    assert n > keep.size // 2
+    return keep
+
+
+def _entrywise_all(orc, w, form, mesh, Ud, Uor, fs, dts, nsub, s0, lam, K, dU, dd, oU, od,
+                   drag="stokes", interp="trilinear"):
+    if form == "fp64":
+        _entrywise(dU, oU, form, "dL/du")
+        _entrywise(dd, od, form, "dL/dd")
+    else:
+        _entrywise_far(orc, w, form, mesh, Ud, Uor, fs, dts, nsub, s0, lam, K, drag, interp,
+                       dd_full=dd)
+
+
 def _target(w, form, x, up, d, U, drag="stokes", interp="trilinear"):
     t = tracker(w, form, drag=drag, interp=interp)
     t.inject(x, up, d * 1.1)
@@ -73,12 +150,14 @@ def test_adjoint_matches_oracle(orc, form, tol, drag):
         assert np.array_equal(before[k], after[k]), f"state restored after backward: {k}"
     dU, dd = dU.cpu().numpy(), dd.cpu().numpy()
     # the oracle differentiates from the GPU's stored initial state
-    oU, od = orc.adjoint(oracle_mesh(w, drag=drag), Uor, s0["x"], s0["up"], s0["d"], w.dt,
-                         w.nsteps, lam)
+    mesh = oracle_mesh(w, drag=drag)
+    oU, od = orc.adjoint(mesh, Uor, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps, lam)
     eU, ed = _rel(dU, oU), _rel(dd, od)
     print(form, drag, "adjoint rel L2: dU", eU, "dd", ed)
     assert eU < tol and ed < tol
     t.close()
+    _entrywise_all(orc, w, form, mesh, [Udev], [Uor], [0] * w.nsteps, [w.dt] * w.nsteps, 1, s0,
+                   lam, 7, dU, dd, oU, od, drag=drag)
 
 
 @pytest.mark.parametrize("form,tol,interp,P", [
@@ -96,12 +175,69 @@ def test_adjoint_ngp_and_crowded_chunks(orc, form, tol, interp, P):
     lam = 2.0 * (S.cpu().numpy() - T)
     dU, dd = t.backward(torch.from_numpy(lam).cuda())
     dU, dd = dU.cpu().numpy(), dd.cpu().numpy()
-    oU, od = orc.adjoint(oracle_mesh(w, interp=1 if interp == "ngp" else 0), Uor, s0["x"],
-                         s0["up"], s0["d"], w.dt, w.nsteps, lam)
+    mesh = oracle_mesh(w, interp=1 if interp == "ngp" else 0)
+    oU, od = orc.adjoint(mesh, Uor, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps, lam)
     eU, ed = _rel(dU, oU), _rel(dd, od)
     print(form, interp, P, "adjoint rel L2: dU", eU, "dd", ed)
     assert eU < tol and ed < tol
     t.close()
+    _entrywise_all(orc, w, form, mesh, [Udev], [Uor], [0] * w.nsteps, [w.dt] * w.nsteps, 1, s0,
+                   lam, 5, dU, dd, oU, od, interp=interp)
+
+
+@pytest.mark.parametrize("form,drag,interp,nsub,fs", [
+    ("fp64", "stokes", "trilinear", 3, [0] * 10),
+    ("fp32_local", "stokes", "trilinear", 3, [0] * 10),
+    ("fp64", "schiller_naumann", "trilinear", 1, [0, 1, 2, 1, 0, 2, 2, 1, 0, 1]),
+    ("fp32_local", "schiller_naumann", "trilinear", 2, [0, 1, 2, 1, 0, 2, 2, 1, 0, 1]),
+    ("fp64", "stokes", "ngp", 3, [0, 1, 1, 0, 1, 0, 0, 1, 1, 0]),
+    ("fp32_local", "schiller_naumann", "ngp", 2, [0, 1, 1, 0, 1, 0, 0, 1, 1, 0])])
+def test_adjoint_substeps_and_fields(orc, form, drag, interp, nsub, fs):
+    """Taped steps of nsub sub-steps each, and taped steps that read
+    different fields (and step lengths): st_backward's dL/du is the sum over
+    the taped sub-steps of the gradient with respect to the field each read,
+    against the oracle's reverse pass over the same sub-steps and fields."""
+    import dataclasses
+    import torch
+    w = _case(P=4000, nsteps=len(fs))
+    if drag == "schiller_naumann":
+        w = dataclasses.replace(w, d_median=60e-6)
+    x, up, d = w.particles()
+    rng = np.random.default_rng(17 + nsub)
+    nf = max(fs) + 1
+    U64 = [w.field()] + [w.field() + rng.normal(0.0, 0.3, size=w.field().shape)
+                         for _ in range(nf - 1)]
+    dts = [w.dt * (1.0 + 0.5 * ((k * 7) % 3 - 1)) for k in range(len(fs))]
+    if form == "fp64":
+        Ud = [torch.from_numpy(u).cuda() for u in U64]
+        Uor = U64
+    else:
+        Ud = [torch.from_numpy(u.astype(np.float32)).cuda() for u in U64]
+        Uor = [u.astype(np.float32).astype(np.float64) for u in U64]
+    ti = "ngp" if interp == "ngp" else "trilinear"
+    tt = tracker(w, form, drag=drag, interp=ti)
+    tt.inject(x, up, d * 1.1)
+    for k, dt in zip(fs, dts):
+        tt.step(Ud[k], dt, nsub=nsub)
+    T = tt.sources().cpu().numpy()
+    tt.close()
+    t = tracker(w, form, drag=drag, interp=ti)
+    t.inject(x, up, d)
+    s0 = state(t)
+    for k, dt in zip(fs, dts):
+        t.step(Ud[k], dt, nsub=nsub, tape=4)
+    lam = 2.0 * (t.sources().cpu().numpy() - T)
+    dU, dd = (g.cpu().numpy() for g in t.backward(torch.from_numpy(lam).cuda()))
+    t.close()
+    mesh = oracle_mesh(w, interp=1 if interp == "ngp" else 0, drag=drag)
+    oU, od = orc.adjoint_run(mesh, np.stack(Uor), fs, dts, nsub, s0["x"], s0["up"], s0["d"], lam)
+    oU = oU.sum(axis=0)
+    tol = 1e-9 if form == "fp64" else 1e-4
+    eU, ed = _rel(dU, oU), _rel(dd, od)
+    print(form, drag, interp, nsub, nf, "adjoint rel L2: dU", eU, "dd", ed)
+    assert eU < tol and ed < tol
+    _entrywise_all(orc, w, form, mesh, Ud, Uor, fs, dts, nsub, s0, lam, 4, dU, dd, oU, od,
+                   drag=drag, interp=ti)
 
 
 def test_checkpoint_interval_does_not_change_gradient():
@@ -206,15 +342,15 @@ def test_autograd_function():
 def test_adjoint_full_size(orc):
     """Forward + adjoint at the differentiation workload's full size: 64^3,
     1e6 droplets, 200 steps of 5e-5 s, checkpoints every 20, FP32
-    chunk-local forward.  A droplet's dL/dd depends only on its own
-    trajectory and on dL/dS_int, so the oracle adjoint of 2000 droplets
-    sampled by id, with the full dL/dS_int, checks dL/dd on them; droplets
-    that the oracle's trajectory brings within 1e-4 cell widths of a face at
-    the start of some step (where the binary32 forward may deposit into the
-    neighbouring cell) are excluded and counted.  dL/du is a sum over every
-    droplet and is checked against the FP64 form's adjoint of the same
-    problem (same field, same dL/dS_int), which the smaller cases pin to
-    the oracle."""
+    chunk-local forward, against the oracle's reverse pass over every droplet
+    (its particle-parallel driver), from the GPU's stored initial state and
+    the binary32 field, with the full dL/dS_int.  A droplet that the oracle's
+    trajectory brings within 1e-4 cell widths of a face at the start of some
+    step may deposit into the neighbouring cell in the binary32 forward; such
+    droplets are left out of the per-droplet dL/dd comparison and counted,
+    and their share of dL/du is what separates the two gradients beyond
+    binary32 rounding.  The FP64 form's adjoint of the same problem is
+    compared with the oracle as well."""
     import torch
     w = workload("adj64")
     x, up, d = w.particles()
@@ -225,32 +361,26 @@ def test_adjoint_full_size(orc):
     lam_dev = torch.from_numpy(lam).cuda()
     dU, dd = [g.cpu().numpy() for g in t.backward(lam_dev)]
     t.close()
-    t64, _, _ = _forward(w, "fp64", x, up, d, torch.from_numpy(Uor).cuda(), K=20)
+    # the FP64 form from the binary32 form's stored initial state, as the oracle
+    t64, _, _ = _forward(w, "fp64", s0["x"], s0["up"], s0["d"], torch.from_numpy(Uor).cuda(),
+                         K=20)
     dU64, dd64 = [g.cpu().numpy() for g in t64.backward(lam_dev)]
     t64.close()
-    eU = _rel(dU, dU64)
 
-    rng = np.random.default_rng(64)
-    idx = np.sort(rng.choice(w.P, 2000, replace=False))
-    xs, us, ds = s0["x"][idx], s0["up"][idx], s0["d"][idx]
     mesh = oracle_mesh(w)
-    h = np.asarray(w.h)
-    near = np.zeros(idx.size, dtype=bool)
-    xo, uo = xs, us
-    for _ in range(w.nsteps):
-        q = xo / h
-        f = q - np.floor(q)
-        near |= (np.minimum(f, 1.0 - f) < 1e-4).any(axis=1)
-        xo, uo, _ = orc.run(mesh, Uor, xo, uo, ds, w.dt, 1)
-    _, od = orc.adjoint(mesh, Uor, xs, us, ds, w.dt, w.nsteps, lam)
-    keep = ~near
-    ed = _rel(dd[idx][keep], od[keep])
-    ed64 = _rel(dd[idx][keep], dd64[idx][keep])
-    print(f"full size: dL/du against the FP64 form {eU:.3e}; dL/dd against the oracle "
-          f"{ed:.3e} on {int(keep.sum())} of {idx.size} sampled droplets "
-          f"({int(near.sum())} near a face excluded), against the FP64 form {ed64:.3e}")
-    assert keep.sum() > idx.size // 2
+    fs, dts = [0] * w.nsteps, [w.dt] * w.nsteps
+    oU, od = orc.adjoint_run_par(mesh, Uor[None], fs, dts, 1, s0["x"], s0["up"], s0["d"], lam)
+    oU = oU[0]
+    eU, ed = _rel(dU, oU), _rel(dd, od)
+    eU64, ed64 = _rel(dU64, oU), _rel(dd64, od)
+    print(f"full size against the oracle over all {w.P} droplets: dL/du {eU:.3e}, dL/dd "
+          f"{ed:.3e}; FP64 form: dL/du {eU64:.3e}, dL/dd {ed64:.3e}")
     assert eU < 1e-4 and ed < 1e-4
+    assert eU64 < 1e-9 and ed64 < 1e-9
+    _entrywise(dU64, oU, "fp64", "dL/du (FP64 form)")
+    _entrywise(dd64, od, "fp64", "dL/dd (FP64 form)")
+    _entrywise_far(orc, w, "fp32_local", mesh, [Udev], [Uor], fs, dts, 1, s0, lam, 20,
+                   dd_full=dd)
 
 
 def test_finite_differences_full_size():

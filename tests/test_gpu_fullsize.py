@@ -10,7 +10,8 @@ balance (sum of sources = minus the particles' drag impulse).
 import numpy as np
 import pytest
 
-from gpu_helpers import BAND, face_distance, fields, min_image, oracle_mesh, tracker, workload
+from gpu_helpers import (BAND, face_distance, fields, lockstep_window, min_image, oracle_mesh,
+                         tracker, workload)
 from oracle.oracle import load as load_oracle
 
 pytestmark = pytest.mark.gpu
@@ -59,6 +60,11 @@ def test_tg128_sampled_parity():
         print("step", step, "pos", pos, "vel", vel, "band", int(near.sum()), "balance", resid)
         assert np.all(resid < 1e-6)
     assert np.array_equal(s1["id"].cpu().numpy(), np.arange(w.P))
+    del s0, s1
+    # one more lockstep step, every source of a 32^3-cell window against the
+    # oracle stepping every droplet that starts the step in it
+    err, k = lockstep_window(t, orc, mesh, Udev, Uor, w.dt, (40, 72, 8), 32, 1e-6)
+    print(f"window of 32^3 cells: {k} droplets, largest source error {err:.3e}")
     t.close()
 
 
@@ -105,10 +111,24 @@ def test_plume512_coupled_sampled_parity():
     Ssum = S.reshape(3, -1).sum(dim=1) * float(np.prod(w.h))
     resid = ((Ssum + J).abs() / scale).cpu().numpy()
     del S
-    t.close()
     orc = load_oracle()
-    xo, uo, _ = orc.run_rotating(oracle_mesh(w), U0, cs, a["x"], a["up"], a["d"], w.dt,
-                                 w.nsteps)
+    mesh = oracle_mesh(w)
+    # one more step with the next field of the schedule (rotated on the host,
+    # rounded to binary32), every source of two windows against the oracle
+    # stepping every droplet that starts the step in them: 16^3 cells at the
+    # plume's centre and 32^3 cells of the uniform background
+    th = np.deg2rad(w.rotate_deg * w.nsteps)
+    Un = np.stack([np.cos(th) * U0[0] - np.sin(th) * U0[1],
+                   np.sin(th) * U0[0] + np.cos(th) * U0[1], U0[2]]).astype(np.float32)
+    Undev = torch.from_numpy(Un).cuda()
+    centre = tuple(int(v) for v in np.floor(w.plume_centres()[0] / w.h))
+    for lo, size in [(tuple(c - 8 for c in centre), 16),
+                     (tuple((c + 256) % 512 for c in centre), 32)]:
+        err, k = lockstep_window(t, orc, mesh, Undev, Un.astype(np.float64), w.dt, lo, size,
+                                 1e-6)
+        print(f"window of {size}^3 cells at {lo}: {k} droplets, largest source error {err:.3e}")
+    t.close()
+    xo, uo, _ = orc.run_rotating(mesh, U0, cs, a["x"], a["up"], a["d"], w.dt, w.nsteps)
     L = np.array(w.L)
     pos = np.abs(min_image(b["x"] - xo, L)).max() / L.max()
     vel = np.abs(b["up"] - uo).max()

@@ -12,7 +12,8 @@ momentum change, per sum of |momentum change|).
 import numpy as np
 import pytest
 
-from gpu_helpers import min_image, oracle_mesh, state, tracker, workload
+from gpu_helpers import (displacement_bound, in_window, lockstep_window, min_image, oracle_mesh,
+                         state, tracker, window_index, workload)
 from oracle.oracle import load as load_oracle
 
 pytestmark = pytest.mark.gpu
@@ -55,14 +56,17 @@ def test_precision_study():
 
 def test_precision_study_full_size():
     """The precision study at its full size: 256^3 mesh, 2e8 droplets in 4
-    plumes, 20 steps.  The oracle cannot step 2e8 droplets, so the binary64
-    form serves as the reference for all of them, and that form is itself
-    checked against the oracle on 20 000 droplets sampled by id, advanced
-    by the oracle from their binary64 initial state over all 20 steps.
-    Reported per binary32 form, over every droplet and cell: worst position
-    error (per L), worst velocity error (m/s), worst per-cell source error
-    (per the largest cell), cell indices that differ from the binary64
-    form's, and the global momentum drift."""
+    plumes, 20 steps.  The binary64 form is checked against the oracle: on
+    20 000 droplets sampled by id, advanced by the oracle from their binary64
+    initial state over all 20 steps; and in every cell of a 12^3-cell window
+    on a plume's flank, the oracle running, over all 20 steps, every droplet
+    that starts close enough to reach the window (the distance a droplet can
+    cover bounds the margin).  It then serves as the reference for all
+    droplets and cells: reported per binary32 form, worst position error (per
+    L), worst velocity error (m/s), worst per-cell source error (per the
+    largest cell), cell indices that differ from the binary64 form's, and the
+    global momentum drift.  Every form also takes one more lockstep step
+    whose sources are checked against the oracle in every cell of a window."""
     import torch
     w = workload("plume256")
     L = np.array(w.L)
@@ -73,6 +77,10 @@ def test_precision_study_full_size():
     s_x, s_d = [], []
     ref = None
     rows = {}
+    orc = load_oracle()
+    mesh = oracle_mesh(w)
+    centre = np.floor(w.plume_centres()[0] / w.h).astype(int)
+    win_lo, win_size = tuple(int(v) for v in centre + np.array([13, 0, 0]) - 6), 12
     for form in ("fp64", "fp32_local", "fp32"):
         t = tracker(w, form)
         for b in range(w.n_device_batches(bsz)):
@@ -85,6 +93,14 @@ def test_precision_study_full_size():
             t.inject(x, up, d)
             del x, up, d
         Ud = torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
+        if form == "fp64":
+            # the droplets that can reach the window within the run
+            s = t.particles()
+            reach = displacement_bound(w, U, 0.0, float(s["d"].max()), w.nsteps, w.dt)
+            margin = int(np.ceil(reach / w.h.min())) + 1
+            sel = in_window(s["cell"], win_lo, win_size, w.n, margin)
+            w_x, w_d = s["x"][sel].cpu().numpy(), s["d"][sel].cpu().numpy()
+            del s, sel
         for _ in range(w.nsteps):
             t.step(Ud, w.dt)
         s = t.particles()
@@ -97,9 +113,18 @@ def test_precision_study_full_size():
                  - w.nsteps * w.dt * g * m.sum())
         drift = float((drift.abs() / mv.abs().sum(dim=0)).max())
         if form == "fp64":
+            _, _, Sw = orc.run_par(mesh, U, w_x, np.zeros_like(w_x), w_d, w.dt, w.nsteps)
+            wi = window_index(win_lo, win_size, w.n)
+            Sg = S.cpu().numpy()
+            werr = max(float(np.abs(Sg[c][wi] - Sw[c][wi]).max() / np.abs(Sw[c][wi]).max())
+                       for c in range(3))
+            print(f"\nfp64 form against the oracle in a {win_size}^3-cell window, all "
+                  f"{w_x.shape[0]} droplets within {margin} cells of it over 20 steps: "
+                  f"largest source error {werr:.3e}")
+            assert werr < 1e-10
+            del Sg
             xs, ds = np.concatenate(s_x), np.concatenate(s_d)
-            orc = load_oracle()
-            xo, uo, _ = orc.run(oracle_mesh(w), U, xs, np.zeros_like(xs), ds, w.dt, w.nsteps)
+            xo, uo, _ = orc.run(mesh, U, xs, np.zeros_like(xs), ds, w.dt, w.nsteps)
             ix = torch.from_numpy(sample).cuda()
             pos = np.abs(min_image(s["x"][ix].cpu().numpy() - xo, L)).max() / L.max()
             vel = np.abs(s["up"][ix].cpu().numpy() - uo).max()
@@ -119,8 +144,15 @@ def test_precision_study_full_size():
             cells = int((s["cell"] != ref["cell"]).any(dim=1).sum())
             rows[form] = (pos, vel, src, cells, drift)
             del s, dx
-        t.close()
-        del S, Ud
+        del S
+        torch.cuda.empty_cache()
+        err, k = lockstep_window(t, orc, mesh, Ud, U if form == "fp64" else
+                                 U.astype(np.float32).astype(np.float64), w.dt,
+                                 (int(centre[0]) - 8, int(centre[1]) - 8, int(centre[2]) - 8), 16,
+                                 {"fp64": 1e-10, "fp32_local": 1e-6, "fp32": 1e-4}[form])
+        print(f"{form}: lockstep step, 16^3 cells at a plume centre, {k} droplets, largest "
+              f"source error {err:.3e}")
+        del Ud
         torch.cuda.empty_cache()
     print("form        pos/L      vel[m/s]   src/max    cells differing  momentum drift")
     for form, r in rows.items():

@@ -169,7 +169,8 @@ def _build_and_pin(name, old, new, tmp):
     with open(csrc, "w") as f:
         f.write(mutated)
     subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-                    csrc, "-o", lib, "-lm"], check=True, capture_output=True)
+                    "-fopenmp", csrc, os.path.join(ROOT, "oracle", "st_oracle_par.c"),
+                    "-I", tmp, "-o", lib, "-lm"], check=True, capture_output=True)
     r = subprocess.run([sys.executable, os.path.join(HERE, "oracle_pins.py"), lib],
                        capture_output=True, text=True, timeout=120)
     out = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else ""
