@@ -298,6 +298,21 @@ st_status st_inject_hilbert(st_ctx *ctx, int32_t order, int64_t nseg, int64_t se
 st_status st_bounding_boxes(st_ctx *ctx, int64_t id0, int64_t per_part, int64_t nparts,
                             double *boxes, int32_t on_device, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * boxes as st_bounding_boxes, computed without any allocation.  The kernels
+ * accumulate the bounds in a fixed device array of the library (one per GPU,
+ * room for ST_NOALLOC_MAX_PARTS partitions, 3 MiB, held until the process
+ * ends), which is then copied to `boxes` (device memory when on_device, else
+ * host memory, and the call then synchronises the stream).  nparts above
+ * ST_NOALLOC_MAX_PARTS gives ST_ERR_INVALID, as do the argument errors of
+ * st_bounding_boxes.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams, other host threads, other contexts)
+ * race, and the caller must order them. */
+#define ST_NOALLOC_MAX_PARTS 65536
+st_status st_bounding_boxes_noalloc(st_ctx *ctx, int64_t id0, int64_t per_part, int64_t nparts,
+                                    double *boxes, int32_t on_device, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,7 +68,9 @@ SIGNATURES = {
     "st_hilbert_positions": (_I, [_P, _I32, _I64, _I64, _I64, _I64, _P, _P, _I32, _P]),
     "st_inject_hilbert": (_I, [_P, _I32, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P]),
     "st_bounding_boxes": (_I, [_P, _I64, _I64, _I64, _P, _I32, _P]),
+    "st_bounding_boxes_noalloc": (_I, [_P, _I64, _I64, _I64, _P, _I32, _P]),
 }
+NOALLOC_MAX_PARTS = 65536
 EXTRAPOLATORS = {"zero": 0, "const": 1, "linear": 2}
 
 _lib = None

@@ -191,6 +191,9 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     if (ok != hipSuccess)
         return dev_bad(ST_ERR_OOM, "device allocation failed after " + std::to_string(total) +
                                        " bytes");
+    // this device's address of the fixed scratch of st_bounding_boxes_noalloc
+    e = st::noalloc_scratch_init(device);
+    if (e != hipSuccess) return dev_bad(ST_ERR_DEVICE, hipGetErrorString(e));
     hipStream_t s = nullptr;
     e = st::launch_init(c, s);
     if (e == hipSuccess) e = st::launch_zero_sources(c, s);
@@ -750,5 +753,30 @@ st_status st_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64_t np
     (void)hipStreamSynchronize(s);
     (void)hipFree(tmp);
     if (e != hipSuccess) return dev_fail(c, e, "st_bounding_boxes");
+    return ST_OK;
+}
+
+st_status st_bounding_boxes_noalloc(st_ctx *c, int64_t id0, int64_t per_part, int64_t nparts,
+                                    double *boxes, int32_t on_device, void *hip_stream)
+{
+    if (!c) return ST_ERR_INVALID;
+    if (!boxes) return fail(c, ST_ERR_INVALID, "st_bounding_boxes_noalloc: null array");
+    if (id0 < 0 || per_part < 1 || nparts < 1)
+        return fail(c, ST_ERR_INVALID,
+                    "st_bounding_boxes_noalloc: need id0 >= 0, per_part >= 1, nparts >= 1");
+    if (nparts > st::kNoAllocMaxParts)
+        return fail(c, ST_ERR_INVALID, "st_bounding_boxes_noalloc: nparts " +
+                                           std::to_string(nparts) + " exceeds the maximum " +
+                                           std::to_string(st::kNoAllocMaxParts));
+    ST_HIP(hipSetDevice(c->device));
+    double *sc = nullptr;
+    ST_HIP(st::noalloc_scratch(c->device, &sc));
+    hipStream_t s = (hipStream_t)hip_stream;
+    st_status r = ensure_flushed(c, s);
+    if (r != ST_OK) return r;
+    ST_HIP(st::launch_bounding_boxes(c, id0, per_part, nparts, sc, s));
+    ST_HIP(hipMemcpyAsync(boxes, sc, (size_t)nparts * 48,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!on_device) ST_HIP(hipStreamSynchronize(s));
     return ST_OK;
 }

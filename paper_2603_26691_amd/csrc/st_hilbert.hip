@@ -17,6 +17,16 @@
 // returns them).
 #include "st_internal.h"
 
+#include <mutex>
+
+// Partial results of st_bounding_boxes_noalloc (the min and max bounds of up
+// to kNoAllocMaxParts boxes, as ordered integer images of binary64): a fixed
+// device array, one copy per GPU, held until the process ends, so that the
+// call allocates nothing.  Host code never passes this name to a kernel or a
+// copy (on the host it is a stand-in, not a device address); it uses the
+// per-device address that noalloc_scratch_init takes.
+static __device__ __align__(256) unsigned long long scratch[st::kNoAllocMaxParts * 6];
+
 namespace st {
 namespace {
 
@@ -230,6 +240,32 @@ hipError_t launch_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64
     else run(float(0));
     hipLaunchKernelGGL(k_bbox_finish, dim3(blocks_for(nparts)), dim3(256), 0, s, b, nparts);
     return hipGetLastError();
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+hipError_t noalloc_scratch(int device, double **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *ptr = g_scratch_ptr[device];
+    return *ptr ? hipSuccess : hipErrorNotInitialized;
 }
 
 }  // namespace st

@@ -25,6 +25,8 @@ constexpr int kSeg = 16384;       // max particles per step work item
 constexpr int kSlackMin = 32;     // spare-slot weight per chunk in the room formula
 constexpr int kMoverStage = 512;  // movers per workgroup staged in LDS
 constexpr int kAlign = 4;         // chunk rooms are whole multiples of this
+// partitions st_bounding_boxes_noalloc can take (its fixed device scratch)
+constexpr int64_t kNoAllocMaxParts = 65536;
 
 template <class T>
 struct View {
@@ -198,5 +200,11 @@ hipError_t launch_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_beg
                                     const double *u, double *x, hipStream_t s);
 hipError_t launch_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64_t nparts,
                                  double *box, hipStream_t s);
+// The fixed device array of st_bounding_boxes_noalloc (st_hilbert.hip):
+// noalloc_scratch_init takes this device's address of it (the device must be
+// current; once per device, later calls return at once); noalloc_scratch
+// returns that address, or an error if it was never taken.
+hipError_t noalloc_scratch_init(int device);
+hipError_t noalloc_scratch(int device, double **ptr);
 
 }  // namespace st

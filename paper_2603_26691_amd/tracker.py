@@ -150,6 +150,24 @@ class Tracker:
                                           _dptr(out), 1, _stream()), self.ctx)
         return out
 
+    def bounding_boxes_noalloc(self, id0, per_part, nparts, out=None):
+        """The boxes of bounding_boxes() from the library's allocation-free
+        entry point (at most NOALLOC_MAX_PARTS partitions): into `out`, a
+        float64 [nparts, 6] device tensor or host numpy array, made on the
+        device when None."""
+        if out is None:
+            out = torch.empty((nparts, 6), dtype=torch.float64, device=self.device)
+        if isinstance(out, torch.Tensor):
+            assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+            assert out.numel() >= 6 * nparts
+            ptr, on_device = _dptr(out), 1
+        else:
+            assert out.dtype == np.float64 and out.flags.c_contiguous and out.size >= 6 * nparts
+            ptr, on_device = ctypes.c_void_p(out.ctypes.data), 0
+        N.check(N.lib().st_bounding_boxes_noalloc(self.ctx, int(id0), int(per_part), int(nparts),
+                                                  ptr, on_device, _stream()), self.ctx)
+        return out
+
     def count(self):
         v = ctypes.c_int64()
         N.check(N.lib().st_count(self.ctx, ctypes.byref(v)), self.ctx)
