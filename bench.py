@@ -1,24 +1,29 @@
 """Benchmark of the per-particle time step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload tg128] [--form fp32_local]
-                [--drag stokes] [--no-fp64] [--no-sn] [--no-hilbert] [--no-adjoint] [--no-scale]
-                [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-plume256] [--no-tg128]
+                [--no-hilbert] [--no-adjoint] [--no-cpu]
 
 A step is one pass of the whole hot path (gather, integrate, deposit,
-relocate and re-bin) over every particle of the workload.  Inputs are
-seeded synthetic data resident in HBM before the timed region starts; K
-steps are timed with events on the stream the kernels run on, bracketed by
-device synchronisations, and a second pass of K steps times the step kernel
-itself with events attached to each of its launches.  Prints one JSON line with the whole-job
-particle-steps/s, the step kernel's roofline figures, and beside them: the
-FP64 form on the same workload, the same run with Schiller-Naumann drag,
-Hilbert-segment placement and partition bounding boxes, forward+adjoint
-throughput (64^3, 1e6 particles, checkpoints every 20 steps), the
-1.4e9-particle 512^3 run with
-the field update on a second stream, and the FP64 oracle timed on this
-host's cores on a bounded sample of the workload.  Next to the published
-HBM peak, the rate of a plain 1 GiB device copy is measured in the same run
-as the practical streaming ceiling.
+relocate and re-bin) over every particle of the workload.  The headline is
+the largest single-GPU workload: 512^3 cells, 1.4e9 droplets (60 % in one
+plume), FP32 chunk-local form, the fluid field rotated by 1 degree per step on
+a second stream that runs one step ahead of the particles.  W coupled
+warm-up steps, then K coupled steps timed with events on the stream the
+kernels run on, bracketed by device synchronisations; the step kernel's own
+duration comes from a pair of events attached to each of its launches in the
+same timed steps.  Inputs are seeded synthetic data resident in HBM before
+the timed region starts.
+
+Printed as one JSON line: the whole-job particle-steps/s, the step kernel's
+roofline (algorithmic bytes per launch over its average launch time) and the
+whole step's (the same bytes over the whole step's time), and beside them:
+the FP64 form on the same workload, the 256^3 precision-study workload in
+both forms, the 128^3 workload, Hilbert-segment placement and partition
+bounding boxes, forward+adjoint throughput (64^3, 1e6 droplets, checkpoints
+every 20 steps), a plain streaming copy of 1 GiB with the particle state's
+access pattern (the practical streaming ceiling beside the published HBM
+peak), and the FP64 oracle timed on this host's cores on a bounded sample of
+the headline workload.
 """
 import argparse
 import json
@@ -30,6 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = ("particle-steps/s on 1 MI355X (fwd, fwd+adjoint) vs FP64 form; "
+          "% of HBM roofline")
 
 
 def algorithmic_bytes(form, particles, items, E=8):
@@ -64,8 +71,25 @@ def inject_device(t, w):
         del x, up, d
 
 
+def inject(t, w):
+    if w.P > 50_000_000:
+        inject_device(t, w)   # too many to draw on the host in time
+    else:
+        inject_host(t, w)
+
+
+_FIELDS = {}
+
+
+def host_field(w):
+    """The workload's cell-centred field (binary64, host), drawn once."""
+    if w.name not in _FIELDS:
+        _FIELDS[w.name] = w.field()
+    return _FIELDS[w.name]
+
+
 def field_of(torch, np, w, form):
-    U = w.field()
+    U = host_field(w)
     return torch.from_numpy(U if form == "fp64" else U.astype(np.float32)).cuda()
 
 
@@ -75,7 +99,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2603_26691_amd", "csrc", "st_device.hi
 def measured_traffic(workload, form):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     record (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
-    plain 1 GiB device copy), or None when there is no record for this
+    plain 1 GiB streaming copy), or None when there is no record for this
     workload or the kernel source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"k_step_{workload}_{form}_counters.txt")
@@ -92,34 +116,47 @@ def measured_traffic(workload, form):
     return float(rec["hbm_bytes_per_launch"])
 
 
-def roofline(form, w, kernel_ms, launches, items, drag="stokes"):
+def roofline(form, w, kernel_ms, launches, items, ms_per_step, drag="stokes"):
+    """The step kernel's roofline (its algorithmic bytes per launch over its
+    average launch duration) and the whole step's (the same bytes over the
+    whole step's duration: every other launch of the step is overhead)."""
     bytes_launch, per_p, per_item = algorithmic_bytes(form, w.P, items, w.chunk_edge)
     avg_s = kernel_ms / max(launches, 1) / 1e3
     achieved = bytes_launch / avg_s / 1e9
+    step_gbps = bytes_launch / (ms_per_step / 1e3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w.name, form) if drag == "stokes" else None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(w.name, form) if drag == "stokes" else None,
             "kernel": "k_step", "avg_kernel_ms": avg_s * 1e3, "bytes_per_launch": bytes_launch,
-            "kernel_timing": "events attached to each step-kernel launch",
-            "model": f"{per_p} B/particle + {per_item} B/work item, {items} items"}
+            "kernel_timing": "events attached to each step-kernel launch of the timed steps",
+            "model": f"{per_p} B/particle + {per_item} B/work item, {items} items",
+            "whole_step": {"achieved": step_gbps, "frac": step_gbps / HBM_PEAK_GBS,
+                           "ms_per_step": ms_per_step}}
 
 
-def device_copy_gbps(torch, mib=1024, reps=20):
-    """Bytes read + written per second by a plain device-to-device copy of
-    `mib` MiB (torch's copy kernel): what streaming HBM traffic reaches in
-    practice, beside the published peak."""
+def stream_copy_gbps(torch, N, mib=1024, reps=20):
+    """Bytes read + written per second by a plain streaming copy of `mib` MiB
+    with the particle state's access pattern (st_stream_copy: one 16-byte
+    non-temporal load and store per thread)."""
+    import ctypes
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    copy = lambda: N.check(N.lib().st_stream_copy(ctypes.c_void_p(a.data_ptr()),  # noqa: E731
+                                                  ctypes.c_void_p(b.data_ptr()), 4 * n, s),
+                           None, "st_stream_copy")
     for _ in range(3):
-        b.copy_(a)
+        copy()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        b.copy_(a)
+        copy()
     e1.record()
     torch.cuda.synchronize()
+    assert torch.equal(a[:1024], b[:1024])
     gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del a, b
     torch.cuda.empty_cache()
@@ -127,23 +164,18 @@ def device_copy_gbps(torch, mib=1024, reps=20):
 
 
 def time_steps(torch, t, U, dt, steps, warmup):
-    """(ms for `steps` steps, summed step-kernel ms, launches).  The steps are
-    timed without per-launch instrumentation; the step kernel's own duration
-    comes from a second pass of `steps` steps with a pair of events attached to
-    each of its launches (recording them adds about 10 us per step)."""
+    """(ms for `steps` steps, summed step-kernel ms, launches); the kernel's
+    own duration from events attached to its launches in the timed steps."""
     for _ in range(warmup):
         t.step(U, dt)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    t.timing(True)
     e0.record()
     for _ in range(steps):
         t.step(U, dt)
     e1.record()
-    torch.cuda.synchronize()
-    t.timing(True)
-    for _ in range(steps):
-        t.step(U, dt)
     torch.cuda.synchronize()
     kernel_ms, launches = t.timing(False)
     return e0.elapsed_time(e1), kernel_ms, launches
@@ -151,17 +183,49 @@ def time_steps(torch, t, U, dt, steps, warmup):
 
 def leg_forward(pkg, torch, np, w, form, steps, warmup, drag="stokes"):
     t = make_tracker(pkg, w, form, drag)
-    if w.P > 50_000_000:
-        inject_device(t, w)   # too many to draw on the host in time
-    else:
-        inject_host(t, w)
+    inject(t, w)
     U = field_of(torch, np, w, form)
     ms, kernel_ms, launches = time_steps(torch, t, U, w.dt, steps, warmup)
     st = t.stats()
     t.close()
     del U
     torch.cuda.empty_cache()
-    return {"ms": ms, "kernel_ms": kernel_ms, "launches": launches, "stats": st}
+    out = {"workload": w.name, "particles": w.P, "form": form, "steps": steps,
+           "value": w.P * steps / (ms / 1e3), "unit": "particle-steps/s",
+           "ms_per_step": ms / steps,
+           "roofline": roofline(form, w, kernel_ms, launches, st["items"], ms / steps, drag),
+           "last_step_movers": st["movers"], "holes": st["holes"], "repacks": st["repacks"]}
+    return out
+
+
+def leg_coupled(pkg, torch, np, w, form, steps, warmup):
+    """The coupled run: W warm-up steps, then K timed steps, the field of step k
+    rotated by k degrees on the second stream while the particles step."""
+    t0 = time.perf_counter()
+    t = make_tracker(pkg, w, form)
+    inject_device(t, w)
+    U0 = field_of(torch, np, w, form)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    if warmup:
+        t.run_coupled(U0, w.rotation(warmup), w.dt)
+    t.timing(True)
+    field_ms, step_ms, total_ms = t.run_coupled(U0, w.rotation(steps, first=warmup), w.dt)
+    kernel_ms, launches = t.timing(False)
+    st = t.stats()
+    t.close()
+    del U0
+    torch.cuda.empty_cache()
+    ms = total_ms / steps
+    return {"workload": w.name, "particles": w.P, "form": form, "steps": steps,
+            "value": w.P * steps / (total_ms / 1e3), "unit": "particle-steps/s",
+            "ms_per_step": ms, "field_update_ms_per_step": field_ms / steps,
+            "particle_step_ms_per_step": step_ms / steps,
+            "overlap": "total vs field + particle stream time: "
+                       f"{total_ms:.2f} ms vs {field_ms + step_ms:.2f} ms",
+            "roofline": roofline(form, w, kernel_ms, launches, st["items"], ms),
+            "last_step_movers": st["movers"], "holes": st["holes"], "repacks": st["repacks"],
+            "setup_s": setup_s}
 
 
 def leg_adjoint(pkg, torch, np, synth):
@@ -187,30 +251,31 @@ def leg_adjoint(pkg, torch, np, synth):
         tt.step(U, w.dt)
     T = tt.sources()
     tt.close()
-    t = make_tracker(pkg, w, "fp32_local")
-    inject_host(t, w)
-    torch.cuda.synchronize()
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    e0.record()
-    for _ in range(w.nsteps):
-        t.step(U, w.dt, tape=20)
-    S = t.sources()
-    e1.record()
-    lam = (2.0 * (S - T)).contiguous()  # dL/dS of L = |S - T|^2
-    dU, dd = t.backward(lam)
-    e2.record()
-    torch.cuda.synchronize()
-    fwd_ms, bwd_ms = e0.elapsed_time(e1), e1.elapsed_time(e2)
-    t.close()
+
+    def run(form, Uf, lam_given=None):
+        t = make_tracker(pkg, w, form)
+        inject_host(t, w)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        for _ in range(w.nsteps):
+            t.step(Uf, w.dt, tape=20)
+        S = t.sources()
+        e1.record()
+        lam = (2.0 * (S - T)).contiguous()  # dL/dS of L = |S - T|^2
+        if lam_given is not None:
+            lam = lam_given
+        dU, dd = t.backward(lam)
+        e2.record()
+        torch.cuda.synchronize()
+        t.close()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), lam, dU, dd
+
+    fwd_ms, bwd_ms, lam, dU, dd = run("fp32_local", U)
     # the same problem in the FP64 form (the field widened from binary32, the
-    # same dL/dS), untimed: how far the binary32 forward moves the gradient
-    t64 = make_tracker(pkg, w, "fp64")
-    inject_host(t64, w)
-    U64 = U.double()
-    for _ in range(w.nsteps):
-        t64.step(U64, w.dt, tape=20)
-    dU64, dd64 = t64.backward(lam)
-    t64.close()
+    # same dL/dS), timed too, and how far the binary32 forward moves the
+    # gradient
+    fwd64, bwd64, _, dU64, dd64 = run("fp64", U.double(), lam)
     rel = {"dL_du": float((dU - dU64).norm() / dU64.norm()),
            "dL_dd": float((dd - dd64).norm() / dd64.norm())}
     value = w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3)
@@ -224,6 +289,8 @@ def leg_adjoint(pkg, torch, np, synth):
             "model_GBps": value * model_b / 1e9,
             "model_frac_of_peak": value * model_b / 1e9 / HBM_PEAK_GBS,
             "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "fp64_form": {"value": w.P * w.nsteps / ((fwd64 + bwd64) / 1e3),
+                          "forward_ms": fwd64, "backward_ms": bwd64},
             "loss": "L2 misfit of the source field against that of diameters x 1.1",
             "grad_finite": bool(torch.isfinite(dU).all() and torch.isfinite(dd).all()),
             "grad_rel_l2_vs_fp64_form": rel}
@@ -277,80 +344,62 @@ def leg_hilbert(pkg, torch, np, w, reps=10):
             "mean_box_volume_fraction": vol}
 
 
-def leg_scale(pkg, torch, np, synth):
-    """512^3, 1.4e9 particles (60 % in one plume), field rotated 1 degree per
-    step on the second stream: throughput, overlap and the step kernel's
-    roofline at full size."""
-    w = synth.get("plume512")
-    t0 = time.perf_counter()
-    t = make_tracker(pkg, w, "fp32_local")
-    inject_device(t, w)
-    U0 = field_of(torch, np, w, "fp32_local")
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    cs = w.rotation()
-    t.run_coupled(U0, w.rotation(2), w.dt)  # warm-up: two steps
-    t.timing(True)
-    field_ms, step_ms, total_ms = t.run_coupled(U0, cs, w.dt)
-    kernel_ms, launches = t.timing(False)
-    st = t.stats()
-    t.close()
-    del U0
-    torch.cuda.empty_cache()
-    return {"workload": w.name, "particles": w.P, "steps": w.nsteps, "form": "fp32_local",
-            "value": w.P * w.nsteps / (total_ms / 1e3), "unit": "particle-steps/s",
-            "ms_per_step": total_ms / w.nsteps, "field_update_ms_per_step": field_ms / w.nsteps,
-            "particle_step_ms_per_step": step_ms / w.nsteps,
-            "overlap": "total vs field + particle stream time: "
-                       f"{total_ms:.2f} ms vs {field_ms + step_ms:.2f} ms",
-            "roofline": roofline("fp32_local", w, kernel_ms, launches, st["items"]),
-            "last_step_movers": st["movers"], "setup_s": setup_s}
-
-
-def cpu_baseline(w, np, steps=4, max_particles=4_000_000):
-    from oracle.oracle import MeshParams, load
+def cpu_baseline(w, np, steps=10, sample=24_000_000, single_sample=1_500_000):
+    """The FP64 oracle on this host: its particle-parallel driver on all the
+    host's cores (OMP_NUM_THREADS, else the cores, at most 16) over the first
+    `sample` droplets of the workload for `steps` steps with the binary32
+    field widened; and the serial oracle on one core over the first
+    `single_sample` droplets."""
+    from oracle.oracle import MeshParams, default_threads, load
     orc = load()
-    k = min(w.P, max_particles)
-    x, up, d = w.particles(k)
-    # the oracle gets the field the binary32 forms use, promoted
-    U = w.field().astype(np.float32).astype(np.float64)
+    U = host_field(w).astype(np.float32).astype(np.float64)
     mesh = MeshParams(**w.mesh_kwargs())
+    x, up, d = w.particles(sample)
+    threads = default_threads()
+    out = None
+    while threads >= 1:
+        try:
+            t0 = time.perf_counter()
+            orc.run_par(mesh, U, x, up, d, w.dt, steps, threads=threads)
+            sec = time.perf_counter() - t0
+            out = {"value": sample * steps / sec, "unit": "particle-steps/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": f"first {sample} droplets of {w.name} (its recipe, drawn on the "
+                             f"host), {steps} steps, FP64 C oracle split over {threads} threads "
+                             "with per-thread source arrays"}
+            break
+        except MemoryError:
+            threads //= 2
     t0 = time.perf_counter()
-    orc.run(mesh, U, x, up, d, w.dt, steps)
-    sec = time.perf_counter() - t0
-    return {"value": k * steps / sec, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {k} particles of {w.name}, {steps} steps, single-threaded FP64 C"}
+    orc.run(mesh, U, x[:single_sample], up[:single_sample], d[:single_sample], w.dt, steps)
+    sec1 = time.perf_counter() - t0
+    single = {"value": single_sample * steps / sec1, "cores": 1,
+              "sample": f"first {single_sample} droplets, {steps} steps, serial oracle"}
+    if out is None:
+        out = dict(single, unit="particle-steps/s", kind="oracle")
+    out["single_core"] = single
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="tg128")
-    ap.add_argument("--form", default="fp32_local")
-    ap.add_argument("--drag", default="stokes", choices=["stokes", "schiller_naumann"])
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form leg")
-    ap.add_argument("--no-sn", action="store_true", help="skip the Schiller-Naumann leg")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form legs")
+    ap.add_argument("--no-plume256", action="store_true", help="skip the 256^3 legs")
+    ap.add_argument("--no-tg128", action="store_true", help="skip the 128^3 legs")
     ap.add_argument("--no-hilbert", action="store_true",
                     help="skip the Hilbert placement and bounding-box leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
-    ap.add_argument("--no-scale", action="store_true", help="skip the 1.4e9-particle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default=None,
+                    help="run one forward leg alone: plume512, plume256, plume256_fp64, "
+                         "tg128 (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB three times (the reference "
+                    help="only run the streaming copy of MIB MiB three times (the reference "
                          "for scaling hardware byte counters) and exit")
     args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        n = args.copy_calibration * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
-        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE "
@@ -360,61 +409,93 @@ def main():
     import numpy as np
     import torch
     import paper_2603_26691_amd as pkg
+    from paper_2603_26691_amd import _native as N
     from workloads import synth
 
-    w = synth.get(args.workload)
-    steps = args.steps if args.steps is not None else w.nsteps
-    res = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup, args.drag)
-    value = w.P * steps / (res["ms"] / 1e3)
-    form_name = {"fp64": "FP64 form", "fp32_local": "FP32 chunk-local form",
-                 "fp32": "FP32 form"}[args.form]
+    if args.copy_calibration:
+        import ctypes
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for _ in range(3):
+            N.check(N.lib().st_stream_copy(ctypes.c_void_p(a.data_ptr()),
+                                           ctypes.c_void_p(b.data_ptr()), 4 * n, s))
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.only:
+        name = args.only.replace("_fp64", "")
+        form = "fp64" if args.only.endswith("_fp64") else "fp32_local"
+        w = synth.get(name)
+        if name == "plume512":
+            r = leg_coupled(pkg, torch, np, w, form, args.steps, args.warmup)
+        else:
+            r = leg_forward(pkg, torch, np, w, form, args.steps, args.warmup)
+        print(json.dumps(r), flush=True)
+        return
+
+    w = synth.get("plume512")
+    head = leg_coupled(pkg, torch, np, w, "fp32_local", args.steps, args.warmup)
     out = {
-        "metric": f"particle-steps/s on 1 MI355X (fwd), {form_name}",
-        "value": value,
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": res["ms"] / steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.form == "fp64" else "f32",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "mesh": list(w.n), "particles": w.P, "dt": w.dt,
-                   "form": args.form, "chunk_edge": w.chunk_edge, "drag": args.drag,
-                   "source_accumulation": "f32" if args.form == "fp32" else "f64",
+                   "form": "fp32_local", "chunk_edge": w.chunk_edge, "drag": "stokes",
+                   "source_accumulation": "f64", "plume_fraction": w.plume_fraction,
+                   "coupling": "field rotated 1 degree per step on a second stream, one step "
+                               "ahead of the particles",
                    "parallelism": "single GPU"},
-        "roofline": roofline(args.form, w, res["kernel_ms"], res["launches"],
-                             res["stats"]["items"], args.drag),
-        "step_kernel_share": res["kernel_ms"] / res["ms"],
-        "device_copy": {"GBps": device_copy_gbps(torch), "bytes": "1 GiB read + 1 GiB written",
-                        "frac_of_peak": None},
-        "last_step_movers": res["stats"]["movers"],
-        "repacks": res["stats"]["repacks"],
+        "roofline": head["roofline"],
+        "coupled": {k: head[k] for k in ("field_update_ms_per_step", "particle_step_ms_per_step",
+                                         "overlap", "last_step_movers", "holes", "repacks",
+                                         "setup_s")},
     }
-    if not args.no_fp64 and args.form != "fp64":
-        r64 = leg_forward(pkg, torch, np, w, "fp64", steps, args.warmup, args.drag)
-        out["fp64_form"] = {"value": w.P * steps / (r64["ms"] / 1e3),
-                            "ms_per_step": r64["ms"] / steps,
-                            "avg_kernel_ms": r64["kernel_ms"] / max(r64["launches"], 1)}
-        out["speedup_vs_fp64_form"] = value / out["fp64_form"]["value"]
-    if not args.no_sn and args.drag == "stokes":
-        rsn = leg_forward(pkg, torch, np, w, args.form, steps, args.warmup, "schiller_naumann")
-        out["schiller_naumann"] = {
-            "value": w.P * steps / (rsn["ms"] / 1e3), "ms_per_step": rsn["ms"] / steps,
-            "roofline": roofline(args.form, w, rsn["kernel_ms"], rsn["launches"],
-                                 rsn["stats"]["items"], "schiller_naumann")}
-    if not args.no_hilbert:
-        out["hilbert"] = leg_hilbert(pkg, torch, np, w)
+    out["stream_copy"] = {"GBps": stream_copy_gbps(torch, N),
+                          "bytes": "1 GiB read + 1 GiB written, 16-byte non-temporal accesses"}
+    out["stream_copy"]["frac_of_peak"] = out["stream_copy"]["GBps"] / HBM_PEAK_GBS
+    out["roofline"]["frac_of_stream_copy"] = out["roofline"]["achieved"] / out["stream_copy"]["GBps"]
+    if not args.no_fp64:
+        # the FP64 form of the same run needs about 245 GB; where it does not
+        # fit, the reason is reported instead
+        try:
+            r64 = leg_coupled(pkg, torch, np, w, "fp64", args.steps, args.warmup)
+            out["fp64_form"] = {k: r64[k] for k in ("value", "ms_per_step", "roofline")}
+            out["speedup_vs_fp64_form"] = out["value"] / r64["value"]
+        except (N.STError, RuntimeError) as e:
+            out["fp64_form"] = {"value": None, "reason": str(e)[:200]}
+            torch.cuda.empty_cache()
+    if not args.no_plume256:
+        w256 = synth.get("plume256")
+        out["plume256"] = leg_forward(pkg, torch, np, w256, "fp32_local", w256.nsteps, 2)
+        if not args.no_fp64:
+            r = leg_forward(pkg, torch, np, w256, "fp64", w256.nsteps, 2)
+            out["plume256"]["fp64_form"] = {k: r[k] for k in ("value", "ms_per_step", "roofline")}
+            out["plume256"]["speedup_vs_fp64_form"] = out["plume256"]["value"] / r["value"]
+    if not args.no_tg128:
+        w128 = synth.get("tg128")
+        out["tg128"] = leg_forward(pkg, torch, np, w128, "fp32_local", 20, 3)
+        if not args.no_fp64:
+            r = leg_forward(pkg, torch, np, w128, "fp64", 20, 3)
+            out["tg128"]["fp64_form"] = {k: r[k] for k in ("value", "ms_per_step", "roofline")}
+        r = leg_forward(pkg, torch, np, w128, "fp32_local", 20, 3, "schiller_naumann")
+        out["tg128"]["schiller_naumann"] = {k: r[k] for k in ("value", "ms_per_step", "roofline")}
+        if not args.no_hilbert:
+            out["hilbert"] = leg_hilbert(pkg, torch, np, w128)
     if not args.no_adjoint:
         out["fwd_adjoint"] = leg_adjoint(pkg, torch, np, synth)
-    if not args.no_scale:
-        out["scale_512"] = leg_scale(pkg, torch, np, synth)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, np)
-    out["device_copy"]["frac_of_peak"] = out["device_copy"]["GBps"] / HBM_PEAK_GBS
-    out["roofline"]["frac_of_device_copy"] = out["roofline"]["achieved"] / out["device_copy"]["GBps"]
     print(json.dumps(out), flush=True)
 
 

@@ -240,10 +240,12 @@ st_status st_ec_reset(st_ctx *ctx, void *hip_stream);
 
 /* Outside the paper (instrumentation of the re-bin).
  * Counters of the last st_step (host memory): movers, full repacks so far,
- * particles, store slots, work items (chunk runs of the step kernel).  Any
- * pointer may be NULL.  Synchronises the stream. */
+ * particles, store slots, work items (chunk runs of the step kernel), holes
+ * (slots that particles left and no arrival has taken yet; they are skipped
+ * until the next full re-bin).  Any pointer may be NULL.  Synchronises the
+ * stream. */
 st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
-                   int64_t *particles, int64_t *slots, int64_t *items,
+                   int64_t *particles, int64_t *slots, int64_t *items, int64_t *holes,
                    void *hip_stream);
 
 /* Outside the paper (measurement; the paper reports times per step,
@@ -257,6 +259,14 @@ st_status st_stats(st_ctx *ctx, int64_t *last_movers, int64_t *repacks,
  * so far; reading them synchronises the recorded events. */
 st_status st_timing(st_ctx *ctx, int32_t enable, double *kernel_ms,
                     int64_t *launches);
+
+/* Outside the paper (measurement reference).  Copies `bytes` (a multiple of
+ * 16) from src to dst (device memory, 16-byte aligned, not overlapping) with
+ * the access pattern of the particle state in st_step: one 16-byte
+ * non-temporal load and store per thread.  Its rate is the practical ceiling
+ * of streaming traffic beside the published HBM peak.  Ordered on hip_stream;
+ * ST_ERR_INVALID for bad arguments (no context, so no message). */
+st_status st_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
 
 /* Paper Sec. 2.2 (particles initialised along a Hilbert curve whose
  * segments give the initial partitions).

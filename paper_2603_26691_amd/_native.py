@@ -61,7 +61,7 @@ SIGNATURES = {
     "st_run_coupled": (_I, [_P, _P, _P, _I32, _D, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P]),
     "st_stats": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
-                      ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
+                      ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P]),
     "st_timing": (_I, [_P, _I32, ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
     "st_ec_estimate": (_I, [_P, _I32, _P, _P, _I, _P]),
     "st_ec_reset": (_I, [_P, _P]),
@@ -69,6 +69,7 @@ SIGNATURES = {
     "st_inject_hilbert": (_I, [_P, _I32, _I64, _I64, _I64, _I64, _P, _P, _P, _I32, _P]),
     "st_bounding_boxes": (_I, [_P, _I64, _I64, _I64, _P, _I32, _P]),
     "st_bounding_boxes_noalloc": (_I, [_P, _I64, _I64, _I64, _P, _I32, _P]),
+    "st_stream_copy": (_I, [_P, _P, _I64, _P]),
 }
 NOALLOC_MAX_PARTS = 65536
 EXTRAPOLATORS = {"zero": 0, "const": 1, "linear": 2}

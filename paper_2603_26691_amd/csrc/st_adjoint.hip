@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u)
-            if (idv[u] >= 0 && idv[u] < a.count)
+            if (idv[u] >= 0 && idv[u] < a.count && ls[u][0] >= T(0) && ls[u][6] > T(0))
                 for (int k = 0; k < 7; ++k) lr[u][k] = a.adj[8 * idv[u] + k];
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -203,7 +203,8 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             if (q >= q1) continue;
             const int jb = (int)(q - q0);   // entry in the batch
             const int64_t id = idv[u];
-            if (id < 0 || id >= a.count) {  // never in a saved store
+            // a hole: a -1 offset (binary32) or a negated diameter (binary64)
+            if (id < 0 || id >= a.count || !(ls[u][0] >= T(0) && ls[u][6] > T(0))) {
                 if (TRI) rb[jb] = -1;
                 continue;
             }

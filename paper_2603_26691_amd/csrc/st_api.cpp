@@ -47,10 +47,10 @@ hipError_t dalloc(P **p, size_t bytes, size_t &total)
 void free_all(st_ctx *c)
 {
     for (int b = 0; b < 2; ++b)
-        for (int k = 0; k < 8; ++k) (void)hipFree(c->store[b][k]);
-    for (int k = 0; k < 2; ++k) (void)hipFree(c->mov[k]);
-    void *singles[] = {c->base, c->room, c->cnt, c->out_cnt, c->in_cnt, c->cursor,
-                       c->new_cnt, c->nbase, c->nroom, c->hole, c->inbox, c->items, c->nseg,
+        for (int k = 0; k < 8; ++k) (void)hipFree(c->store_raw[b][k]);
+    for (int k = 0; k < 3; ++k) (void)hipFree(c->mov[k]);
+    void *singles[] = {c->base, c->room, c->cnt, c->ndead, c->out_cnt, c->in_cnt, c->cursor,
+                       c->new_cnt, c->nbase, c->nroom, c->hole, c->items, c->nseg,
                        c->scan_tmp, c->room_denom, c->flags, c->src, c->stage64, c->fieldbuf[0],
                        c->fieldbuf[1], c->ec_prev, c->ec_ext};
     for (void *p : singles) (void)hipFree(p);
@@ -165,15 +165,20 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
         if (ok == hipSuccess) ok = dalloc(ptr, bytes, total);
     };
     for (int b = 0; b < 2; ++b) {
-        for (int k = 0; k < 7; ++k) A(&c->store[b][k], (size_t)c->slots * c->tsize);
-        A(&c->store[b][7], (size_t)c->slots * 4);
+        for (int k = 0; k < 8; ++k) {
+            const size_t off = (size_t)(8 * b + k) * st::kStagger;
+            A(&c->store_raw[b][k], (size_t)c->slots * (k < 7 ? c->tsize : 4) + off);
+            if (c->store_raw[b][k]) c->store[b][k] = (char *)c->store_raw[b][k] + off;
+        }
     }
     A(&c->base, (size_t)(C + 1) * 8);
     A(&c->room, (size_t)C * 4);
     A(&c->cnt, (size_t)C * 4);
+    A(&c->ndead, (size_t)C * 4);
     A(&c->mov[0], (size_t)c->mcap * (c->tsize == 8 ? sizeof(st::MoverRec<double>)
                                                    : sizeof(st::MoverRec<float>)));
     A(&c->mov[1], (size_t)c->mcap * 4);
+    A(&c->mov[2], (size_t)c->mcap * 4);
     A(&c->out_cnt, (size_t)C * 4);
     A(&c->in_cnt, (size_t)C * 4);
     A(&c->cursor, (size_t)C * 4);
@@ -181,7 +186,6 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
     A(&c->nbase, (size_t)(C + 1) * 8);
     A(&c->nroom, (size_t)C * 4);
     A(&c->hole, (size_t)c->slots * 4);
-    A(&c->inbox, (size_t)c->slots * 4);
     A(&c->items, (size_t)c->max_items * 8);
     A(&c->nseg, (size_t)(C + 1) * 4);
     A(&c->scan_tmp, (size_t)(C / 1024 + 4) * 8);
@@ -572,7 +576,7 @@ st_status st_ec_estimate(st_ctx *c, int32_t kind, const double *S_last, double *
 }
 
 st_status st_stats(st_ctx *c, int64_t *last_movers, int64_t *repacks, int64_t *particles,
-                   int64_t *slots, int64_t *items, void *hip_stream)
+                   int64_t *slots, int64_t *items, int64_t *holes, void *hip_stream)
 {
     if (!c) return ST_ERR_INVALID;
     ST_HIP(hipSetDevice(c->device));
@@ -585,7 +589,17 @@ st_status st_stats(st_ctx *c, int64_t *last_movers, int64_t *repacks, int64_t *p
     if (particles) *particles = c->count + c->pending;
     if (slots) *slots = c->slots;
     if (items) *items = f[st::F_NITEMS];
+    if (holes) *holes = f[st::F_DEAD];
     return ST_OK;
+}
+
+st_status st_stream_copy(const void *src, void *dst, int64_t bytes, void *hip_stream)
+{
+    if (!src || !dst || bytes < 0 || bytes % 16 != 0 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return ST_ERR_INVALID;
+    if (bytes == 0) return ST_OK;
+    return st::launch_stream_copy(src, dst, bytes, (hipStream_t)hip_stream) == hipSuccess
+               ? ST_OK : ST_ERR_DEVICE;
 }
 
 st_status st_timing(st_ctx *c, int32_t enable, double *kernel_ms, int64_t *launches)

@@ -3,30 +3,38 @@
 // One step of the particle method (paper Sec. 2.1 equations of motion and
 // momentum source, Sec. 2.5 interpolation, deposit and time integration)
 // is five launches:
-//   step      one workgroup per work item (a run of at most kSeg particles of
+//   step      one workgroup per work item (a run of at most kSeg slots of
 //             one chunk): stage the chunk's fluid tile with a one-cell halo
 //             in LDS, gather, integrate, deposit into an LDS accumulator of
 //             the chunk's cells, write every particle back in place, collect
 //             the chunk crossers ("movers") in LDS by direction and emit
 //             them as whole records, with one atomic instruction for all of
-//             a workgroup's reservations (mover list, vacated slots, one
-//             arrival count per neighbouring chunk), and flush the
+//             a workgroup's reservations (mover list, the chunk's hole list,
+//             one arrival count per neighbouring chunk), and flush the
 //             accumulator with one read-modify-write (or one atomic, for
-//             chunks split over several items) per cell.  A mover files
-//             itself in its destination chunk's inbox; arrivals that do not
+//             chunks split over several items) per cell.  A mover's slot
+//             becomes a hole of its chunk (its diameter negated, its state
+//             left in place); its record carries its destination and its
+//             rank among the destination's arrivals.  Arrivals that do not
 //             fit the destination's free slots force the full re-bin;
-//   fill      one wave per chunk (a workgroup for a crowded one): arrivals
-//             and, when the chunk shrank, its tail particles fill the
-//             vacated slots, keeping the chunk dense (or, when a full re-bin
-//             is due, the re-keyed counts);
+//   arrive    one thread per mover: each arrival takes a hole of its
+//             destination (the newest first) or, when there are none left,
+//             the next slot past the destination's last (or, when a full
+//             re-bin is due, the re-keyed counts);
+//   counts    one wave per chunk: the new slot and hole counts; holes no
+//             arrival took get a NaN diameter and are skipped by every
+//             kernel until the next full re-bin (forced once they exceed a
+//             sixteenth of the particles);
 //   layout    work items of the next step from the counts, the reset of the
 //             counters, and, when a full re-bin is due, the rooms and bases
-//             of its layout (one workgroup);
+//             of its layout (one workgroup; it also takes the counts step
+//             when the mesh has few enough chunks);
 //   scatter, commit
 //             only when a chunk ran out of room, the mover list overflowed
 //             or particles were injected: a full counting-sort re-bin into
 //             the second store, copied back (decided on the device).
-// (Meshes of more than kScan1Max chunks scan with several launches.)
+// (Meshes of more than kScan1Max chunks count and scan with several
+// launches.)
 // Device flags that decide between the two re-bins hold the tag (epoch) of
 // the step that raised them, so nothing has to clear them between steps.
 #include "st_internal.h"
@@ -34,6 +42,8 @@
 #include <hip/hip_ext.h>
 
 #include <math.h>
+
+#include <algorithm>
 
 namespace st {
 namespace {
@@ -346,6 +356,7 @@ struct ItemArgs {
     int32_t *out_cnt, *in_cnt, *new_cnt, *cursor;
     int32_t *flags;
     int32_t epoch;
+    int32_t dead_limit;  // more holes than this force a full re-bin at the next step
 };
 
 __device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
@@ -364,6 +375,8 @@ __device__ __forceinline__ void finish_flags(const ItemArgs &a)
     a.flags[F_NITEMS] = a.noff[a.C];
     a.flags[F_LASTMOV] = a.flags[nmov_slot(a.epoch)];
     a.flags[nmov_slot(a.epoch + 1)] = 0;
+    // holes are streamed like particles until a full re-bin drops them
+    if (a.flags[F_DEAD] > a.dead_limit) a.flags[F_FORCE] = a.epoch + 1;
 }
 
 // one workgroup: scan, items and reset (C <= kScan1Max)
@@ -383,13 +396,36 @@ __global__ void k_items(ItemArgs a)
     if (blockIdx.x == 0 && threadIdx.x == 0) finish_flags(a);
 }
 
-// one workgroup, after the fill or the re-keyed count (C <= kScan1Max).  After
-// a fill: the work items of the next step and the reset of the counters.
-// When a full re-bin is due: the rooms and bases of its layout and the item
-// offsets from the re-keyed counts; the scatter still walks the current
-// items, so the commit writes the new ones.
+// After the arrivals: chunk c's new slot and hole counts.  With h holes
+// (older ones plus the step's departures) and `in` arrivals, the arrivals
+// took the top min(h, in) holes and the rest of them extended the chunk;
+// holes no arrival took stay listed (and marked: a -1 offset or a negated
+// diameter).  Returns the chunk's holes.
+template <class T>
+__device__ __forceinline__ int32_t count_chunk(const View<T> &V, const int32_t *out_cnt,
+                                               const int32_t *in_cnt, int64_t c)
+{
+    const int32_t out = out_cnt[c], in = in_cnt[c], nd = V.ndead[c];
+    const int32_t h = nd + out;
+    if (out == 0 && in == 0) return nd;
+    if (in >= h) {
+        V.cnt[c] += in - h;
+        V.ndead[c] = 0;
+        return 0;
+    }
+    V.ndead[c] = h - in;
+    return h - in;
+}
+
+// one workgroup, after the arrivals or the re-keyed count (C <= kScan1Max).
+// After the arrivals: the chunks' new counts (one wave per chunk), the work
+// items of the next step and the reset of the counters.  When a full re-bin
+// is due: the rooms and bases of its layout and the item offsets from the
+// re-keyed counts; the scatter still walks the current items, so the commit
+// writes the new ones.
+template <class T>
 __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, Segments now,
-                                                  Segments rekeyed, ItemArgs a,
+                                                  Segments rekeyed, ItemArgs a, View<T> V,
                                                   const int32_t *flags)
 {
     if (full_rebin(flags, a.epoch)) {
@@ -399,6 +435,12 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
         block_scan_all<int32_t>(rekeyed, a.C, a.noff);
         return;
     }
+    int32_t dead = 0;
+    for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x)
+        dead += count_chunk(V, a.out_cnt, a.in_cnt, c);
+    int32_t total;
+    block_excl_scan<int32_t>(dead, total);   // ends with a barrier: the counts are visible
+    if (threadIdx.x == 0) a.flags[F_DEAD] = total;
     block_scan_all<int32_t>(now, a.C, a.noff);
     __syncthreads();
     for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x) write_items(a, c);
@@ -439,8 +481,7 @@ struct StepArgs {
     int64_t mcap;
     int32_t *out_cnt;
     int32_t *in_cnt;
-    int32_t *hole;
-    int32_t *inbox;          // arrivals of chunk c at inbox[base[c] + rank]
+    int32_t *hole;           // holes of chunk c, relative to base[c], from hole[base[c]]
     int32_t *flags;
     int32_t deposit;         // 0: move and re-bin only (tape recompute)
     int32_t epoch;           // tag of this step in the device flags
@@ -522,33 +563,51 @@ __device__ __forceinline__ const T *at_byte(const T *base, uint32_t byte_off)
     return (const T *)((const char *)base + byte_off);
 }
 
-// A mover already written in place (un-rebased offsets, relative to chunk
-// c): records the vacated slot, marks it, copies the particle, re-based
-// onto its destination chunk, into the mover list at m and files m in the
-// destination's inbox.
+// Slots of chunk c free for arrivals whatever the step's departures: those
+// past its last slot and its holes from earlier steps.
+template <class T>
+__device__ __forceinline__ int32_t free_slots(const View<T> &V, int64_t c)
+{
+    return V.room[c] - V.cnt[c] + V.ndead[c];
+}
+
+// A slot holds a particle unless its offset is negative (binary32 forms:
+// the step kernel stores -1 for a particle that left) or its diameter is not
+// positive (binary64 form: the diameter of a particle that left is negated).
+template <class T>
+__device__ __forceinline__ bool occupied(T ox, T d)
+{
+    return ox >= T(0) && d > T(0);
+}
+
+// A mover not staged in LDS (more movers than the stage holds), from its
+// new state in registers (un-rebased offsets, relative to chunk c): lists
+// its slot q among the chunk's holes at hpos and copies the particle,
+// re-based onto its destination chunk, into the mover list at m with its
+// destination and its rank among the destination's arrivals.  Returns false
+// when the mover list is full: the particle then stays in place (the full
+// re-bin that the overflow forces takes it from there).
 template <class T, class A>
-__device__ __forceinline__ void emit_mover(const StepArgs<T, A> &a, int64_t c, int64_t base,
-                                           int64_t q, int64_t m, int64_t hpos)
+__device__ __forceinline__ bool emit_mover(const StepArgs<T, A> &a, int64_t c, int64_t base,
+                                           int64_t q, int64_t m, int64_t hpos, T x, T y, T z,
+                                           T vx, T vy, T vz, T dd)
 {
     const View<T> &V = a.V;
-    T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-    const T vx = V.vx[q], vy = V.vy[q], vz = V.vz[q], dd = V.d[q];
     const int32_t id = V.id[q];
     const int64_t cn = chunk_after(a.p, c, x, y, z);
-    V.id[q] = -1 - id;
     a.hole[base + hpos] = (int32_t)(q - base);
-    if (m < a.mcap) {
-        a.mv.rec[m] = MoverRec<T>{x, y, z, vx, vy, vz, dd, id};
-        a.mv.dest[m] = (int32_t)cn;
-        const int32_t r = atomicAdd(&a.in_cnt[cn], 1);
-        // arrivals must fit the destination's free slots (room - count, a
-        // bound that ignores its departures); one that does not forces the
-        // full re-bin, and its entry is never read
-        if (r < V.room[cn] - V.cnt[cn]) a.inbox[V.base[cn] + r] = (int32_t)m;
-        else a.flags[F_OVERFLOW] = a.epoch;
-    } else {
+    if (m >= a.mcap) {
         a.flags[F_OVERFLOW] = a.epoch;
+        return false;
     }
+    a.mv.rec[m] = MoverRec<T>{x, y, z, vx, vy, vz, dd, id};
+    a.mv.dest[m] = (int32_t)cn;
+    const int32_t r = atomicAdd(&a.in_cnt[cn], 1);
+    a.mv.rank[m] = r;
+    // arrivals must fit the destination's free slots; one that does not
+    // forces the full re-bin, which places every recorded mover itself
+    if (r >= free_slots(V, cn)) a.flags[F_OVERFLOW] = a.epoch;
+    return true;
 }
 
 // Staged mover: its slot within the work item (below kSeg, 14 bits), its
@@ -577,8 +636,7 @@ __global__ void __launch_bounds__(kBlock)
     constexpr bool kStageVals = sizeof(T) == 4;
     __shared__ T mval[kStageVals ? 6 * kMoverStage : 1];
     __shared__ int32_t mcount, mbase_sh, hbase_sh;
-    __shared__ int32_t dcount[28], doff[28], dbase[27], nb_free[27];
-    __shared__ int64_t nb_base[27];
+    __shared__ int32_t dcount[28], doff[28], dbase[27];
 
     // the grid covers the most items a layout can have, rounded up to whole
     // rounds of the remap
@@ -589,6 +647,7 @@ __global__ void __launch_bounds__(kBlock)
     const int64_t seg = a.items[2 * item + 1];
     const int64_t base = V.base[c];
     const int32_t cnt = V.cnt[c];
+    const int32_t nd_c = V.ndead[c];   // this step's holes are listed after these
     const int64_t s0 = base + seg * kSeg;
     const int64_t s1 = min(s0 + (int64_t)kSeg, base + (int64_t)cnt);
     const bool multi = cnt > kSeg;
@@ -670,7 +729,8 @@ __global__ void __launch_bounds__(kBlock)
         uint32_t movers = 0, dirs = 0;   // mover bits and 5-bit direction classes
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            const bool valid = (int)o + k < nq;
+            // slots past the run and holes hold no particle
+            const bool valid = (int)o + k < nq && occupied(X[k], DD[k]);
             const T xi[3] = {X[k], Y[k], Z[k]};
             const T up[3] = {UX[k], UY[k], UZ[k]};
             const T dp = DD[k];
@@ -747,12 +807,14 @@ __global__ void __launch_bounds__(kBlock)
             // particle that stays needs no re-basing.
             const bool mover = xn[0] < T(0) || xn[0] >= fe || xn[1] < T(0) || xn[1] >= fe ||
                                xn[2] < T(0) || xn[2] >= fe;
-            X[k] = xn[0];
-            Y[k] = xn[1];
-            Z[k] = xn[2];
-            UX[k] = upn[0];
-            UY[k] = upn[1];
-            UZ[k] = upn[2];
+            if (valid) {   // a hole keeps what it holds (binary32: the -1 offset)
+                X[k] = xn[0];
+                Y[k] = xn[1];
+                Z[k] = xn[2];
+                UX[k] = upn[0];
+                UY[k] = upn[1];
+                UZ[k] = upn[2];
+            }
             if (valid && mover) {
                 movers |= 1u << k;
                 T tx = xn[0], ty = xn[1], tz = xn[2];
@@ -764,13 +826,6 @@ __global__ void __launch_bounds__(kBlock)
                 dirs |= (uint32_t)dir << (kDirBits * k);
             }
         }
-        // slots past s1 in the last group are dead; writing them is harmless
-        vst<T, G>(at_byte(pox, ob), X);
-        vst<T, G>(at_byte(poy, ob), Y);
-        vst<T, G>(at_byte(poz, ob), Z);
-        vst<T, G>(at_byte(pvx, ob), UX);
-        vst<T, G>(at_byte(pvy, ob), UY);
-        vst<T, G>(at_byte(pvz, ob), UZ);
         // stage the movers with their direction class: one reservation of
         // stage entries per wave (their ranks within the direction classes
         // are taken after the loop)
@@ -804,10 +859,13 @@ __global__ void __launch_bounds__(kBlock)
                         mval[3 * kMoverStage + j] = UX[k];
                         mval[4 * kMoverStage + j] = UY[k];
                         mval[5 * kMoverStage + j] = UZ[k];
+                        X[k] = T(-1);   // the slot becomes a hole
                     } else {  // more movers than the LDS stage holds: emit directly
                         const int64_t m = atomicAdd(a.nmov, 1);
                         const int64_t h = atomicAdd(&a.out_cnt[c], 1);
-                        emit_mover(a, c, base, s0 + o + k, m, h);
+                        if (emit_mover(a, c, base, s0 + o + k, m, nd_c + h, X[k], Y[k], Z[k],
+                                       UX[k], UY[k], UZ[k], DD[k]))
+                            X[k] = T(-1);
                     }
                     ++j;
                 }
@@ -821,12 +879,22 @@ __global__ void __launch_bounds__(kBlock)
                     } else {  // more movers than the LDS stage holds: emit directly
                         const int64_t m = atomicAdd(a.nmov, 1);
                         const int64_t h = atomicAdd(&a.out_cnt[c], 1);
-                        emit_mover(a, c, base, s0 + o + k, m, h);
+                        // binary64: the negated diameter marks the hole
+                        if (emit_mover(a, c, base, s0 + o + k, m, nd_c + h, X[k], Y[k], Z[k],
+                                       UX[k], UY[k], UZ[k], DD[k]))
+                            a.V.d[s0 + o + k] = -DD[k];
                     }
                     ++j;
                 }
             }
         }
+        // slots past s1 in the last group are dead; writing them is harmless
+        vst<T, G>(at_byte(pox, ob), X);
+        vst<T, G>(at_byte(poy, ob), Y);
+        vst<T, G>(at_byte(poz, ob), Z);
+        vst<T, G>(at_byte(pvx, ob), UX);
+        vst<T, G>(at_byte(pvy, ob), UY);
+        vst<T, G>(at_byte(pvz, ob), UZ);
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             X[k] = Xn[k];
@@ -920,12 +988,9 @@ __global__ void __launch_bounds__(kBlock)
             const int32_t r = atomicAdd(ctr, add);
             if (nb) {
                 dbase[lane] = r;
-                nb_base[lane] = V.base[dc];
-                const int32_t fr = V.room[dc] - V.cnt[dc];
-                nb_free[lane] = fr;
                 // arrivals must fit the destination's free slots (a bound
                 // that ignores its departures), else the full re-bin runs
-                if (r + n > fr) a.flags[F_OVERFLOW] = a.epoch;
+                if (r + n > free_slots(V, dc)) a.flags[F_OVERFLOW] = a.epoch;
             }
             if (lane == 32) mbase_sh = r;
             if (lane == 33) hbase_sh = r;
@@ -959,60 +1024,46 @@ __global__ void __launch_bounds__(kBlock)
         const int rank = w >> (kSlotBits + kDirBits);
         const int64_t m = (int64_t)mbase_sh + doff[dir] + rank;
         // re-base the offsets into the destination chunk
-        const int kx = rebase(mx[u], fe, inv_e);
-        const int ky = rebase(my[u], fe, inv_e);
-        const int kz = rebase(mz[u], fe, inv_e);
+        T rx = mx[u], ry = my[u], rz = mz[u];
+        const int kx = rebase(rx, fe, inv_e);
+        const int ky = rebase(ry, fe, inv_e);
+        const int kz = rebase(rz, fe, inv_e);
         int64_t dest;
         int32_t r;
-        int64_t dbas;
-        int32_t dfree;
         if (dir < 27) {   // within the direction's reservation
             dest = chunk_index(p, wrapi(cx + dir % 3 - 1, p.nc[0]),
                                wrapi(cy + (dir / 3) % 3 - 1, p.nc[1]),
                                wrapi(cz + dir / 9 - 1, p.nc[2]));
             r = dbase[dir] + rank;
-            dbas = nb_base[dir];
-            dfree = nb_free[dir];
         } else {          // farther than one chunk: a reservation of its own
             dest = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
                                wrapi(cz + kz, p.nc[2]));
             r = atomicAdd(&a.in_cnt[dest], 1);
-            dbas = V.base[dest];
-            dfree = V.room[dest] - V.cnt[dest];
-            if (r >= dfree) a.flags[F_OVERFLOW] = a.epoch;
+            if (r >= free_slots(V, dest)) a.flags[F_OVERFLOW] = a.epoch;
         }
-        V.id[s0 + off] = -1 - mid[u];
-        a.hole[base + hbase_sh + j] = (int32_t)(s0 + off - base);
+        // the slot becomes a hole of this chunk (binary32: the step stored a
+        // -1 offset; binary64: the diameter is negated)
+        a.hole[base + nd_c + hbase_sh + j] = (int32_t)(s0 + off - base);
         if (m < a.mcap) {
-            a.mv.rec[m] = MoverRec<T>{mx[u], my[u], mz[u], mvx[u], mvy[u], mvz[u], md[u],
-                                      mid[u]};
+            a.mv.rec[m] = MoverRec<T>{rx, ry, rz, mvx[u], mvy[u], mvz[u], md[u], mid[u]};
             a.mv.dest[m] = (int32_t)dest;
-            // a rank beyond the free slots has forced the full re-bin; its
-            // entry is never read
-            if (r < dfree) a.inbox[dbas + r] = (int32_t)m;
+            // a rank beyond the destination's free slots has forced the full
+            // re-bin, which places every recorded mover itself
+            a.mv.rank[m] = r;
+            if constexpr (!kStageVals) V.d[s0 + off] = -md[u];
         } else {
+            // the mover list is full: the particle stays in place (its
+            // un-rebased offsets) for the full re-bin that this forces
             a.flags[F_OVERFLOW] = a.epoch;
+            if constexpr (kStageVals) V.ox[s0 + off] = mx[u];
         }
     }
 }
 
 
 // ---------------------------------------------------------------------------
-// re-bin after the step: the mover-only fill or the full counting sort
+// re-bin after the step: the arrivals or the full counting sort
 // ---------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void copy_slot(const View<T> &V, int64_t dst, int64_t src)
-{
-    V.ox[dst] = V.ox[src];
-    V.oy[dst] = V.oy[src];
-    V.oz[dst] = V.oz[src];
-    V.vx[dst] = V.vx[src];
-    V.vy[dst] = V.vy[src];
-    V.vz[dst] = V.vz[src];
-    V.d[dst] = V.d[src];
-    V.id[dst] = V.id[src];
-}
-
 template <class T>
 __device__ __forceinline__ void place_mover(const View<T> &V, int64_t dst, const Movers<T> &mv,
                                             int64_t m)
@@ -1034,11 +1085,12 @@ struct RebinArgs {
     View<T> W;               // second store (target of the full re-bin)
     Movers<T> mv;
     int64_t C;
-    const int32_t *out_cnt, *in_cnt, *inbox;
+    const int32_t *out_cnt, *in_cnt;
     int32_t *hole;
     const int32_t *items, *nitems;
     Params p;
     int64_t npend;           // staged injected particles (full re-bin only)
+    int64_t mcap;            // mover list capacity
     int32_t *new_cnt, *cursor;
     const int64_t *nbase;
     const int32_t *nroom;
@@ -1048,116 +1100,43 @@ struct RebinArgs {
     int32_t epoch;
 };
 
-constexpr int kFillBlock = 1024;  // threads per workgroup of the fill
-constexpr int kBigFill = 256;     // chunks with more movers than this get a workgroup
+constexpr int kArriveBlock = 256;   // threads per workgroup of the arrivals
 
-// One workgroup fills one chunk with many movers (same steps as the
-// per-wave fill below, with workgroup-wide scans).
+// One thread per mover of the step: its arrival of rank r in chunk c takes
+// the hole r places from the top of the chunk's hole list (the step's own
+// departures first, then the older holes), or, past the holes, the slot
+// r - holes past the chunk's last.  Counts are those of the step's start
+// (the counts pass runs after this one).
 template <class T>
-__device__ void fill_big_chunk(const RebinArgs<T> &a, int64_t c, int32_t out, int32_t in)
+__device__ void arrive(const RebinArgs<T> &a)
 {
     const View<T> &V = a.V;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t base = V.base[c];
-    const int32_t cnt = V.cnt[c];
-    const int32_t ncnt = cnt - out + in;
-    int32_t *H = a.hole + base;
-    const int32_t *box = a.inbox + base;
-    // every thread has read the old count before thread 0 stores the new
-    // one at the end (the waves of the block arrive here at different times)
-    __syncthreads();
-    if (ncnt >= cnt) {
-        for (int32_t r = tid; r < in; r += nt)
-            place_mover(V, base + (r < out ? H[r] : cnt + (r - out)), a.mv, box[r]);
-    } else {
-        int32_t k = 0;
-        for (int32_t j0 = 0; j0 < out; j0 += nt) {
-            const int32_t j = j0 + tid;
-            const int32_t h = j < out ? H[j] : 0;
-            const int32_t keep = (j < out && h < ncnt) ? 1 : 0;
-            int32_t tot;
-            const int32_t ex = block_excl_scan<int32_t>(keep, tot);
-            if (keep) H[k + ex] = h;   // below every entry a later round reads
-            k += tot;
-        }
-        __syncthreads();
-        for (int32_t r = tid; r < in; r += nt) place_mover(V, base + H[r], a.mv, box[r]);
-        int32_t placed = 0;
-        const int32_t tail = cnt - ncnt;
-        for (int32_t t0 = 0; t0 < tail; t0 += nt) {
-            const int32_t t = t0 + tid;
-            const int64_t slot = base + ncnt + t;
-            const int32_t live = (t < tail && V.id[slot] >= 0) ? 1 : 0;
-            int32_t tot;
-            const int32_t ex = block_excl_scan<int32_t>(live, tot);
-            if (live) copy_slot(V, base + H[in + placed + ex], slot);
-            placed += tot;
-        }
-    }
-    if (tid == 0) V.cnt[c] = ncnt;
-    __syncthreads();
-}
-
-// One wave per chunk: the arrivals, and when the chunk shrank its live tail
-// particles, fill the vacated slots below the new count.  Chunks with more
-// than kBigFill movers are left to a whole workgroup afterwards.
-template <class T>
-__device__ void fill_chunks(const RebinArgs<T> &a)
-{
-    const View<T> &V = a.V;
-    const int lane = __lane_id();
-    const int64_t wpb = blockDim.x >> 6;
-    for (int64_t c = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); c < a.C;
-         c += (int64_t)gridDim.x * wpb) {
-        const int32_t out = a.out_cnt[c], in = a.in_cnt[c];
-        if (out == 0 && in == 0) continue;
-        if (out + in > kBigFill) continue;
+    const int64_t nm = a.flags[nmov_slot(a.epoch)];
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[F_DEAD] = 0;   // summed by the counts
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = a.mv.dest[m];
+        const int32_t r = a.mv.rank[m];
         const int64_t base = V.base[c];
-        const int32_t cnt = V.cnt[c];
-        const int32_t ncnt = cnt - out + in;
-        int32_t *H = a.hole + base;            // chunk-relative vacated slots
-        const int32_t *box = a.inbox + base;   // arrivals, by rank
-        if (ncnt >= cnt) {
-            // every vacated slot lies below the new count: arrivals fill
-            // them first, then extend the chunk
-            for (int32_t r = lane; r < in; r += 64)
-                place_mover(V, base + (r < out ? H[r] : cnt + (r - out)), a.mv, box[r]);
-        } else {
-            // keep the vacated slots below the new count, compacted in place
-            // (a round only writes below the entries it has already read)
-            int32_t k = 0;
-            for (int32_t j0 = 0; j0 < out; j0 += 64) {
-                const int32_t j = j0 + lane;
-                const int32_t h = j < out ? H[j] : 0;
-                const bool keep = j < out && h < ncnt;
-                const uint64_t mask = __ballot(keep);
-                if (keep) H[k + __popcll(mask & lanes_below_mask())] = h;
-                k += __popcll(mask);
-            }
-            __threadfence_block();
-            // arrivals take the first `in` of them
-            for (int32_t r = lane; r < in; r += 64) place_mover(V, base + H[r], a.mv, box[r]);
-            // live particles beyond the new count take the rest
-            int32_t placed = 0;
-            const int32_t tail = cnt - ncnt;
-            for (int32_t t0 = 0; t0 < tail; t0 += 64) {
-                const int32_t t = t0 + lane;
-                const int64_t slot = base + ncnt + t;
-                const bool live = t < tail && V.id[slot] >= 0;
-                const uint64_t mask = __ballot(live);
-                if (live) copy_slot(V, base + H[in + placed + __popcll(mask & lanes_below_mask())], slot);
-                placed += __popcll(mask);
-            }
-        }
-        if (lane == 0) V.cnt[c] = ncnt;
-    }
-    for (int64_t c = blockIdx.x; c < a.C; c += gridDim.x) {
-        const int32_t out = a.out_cnt[c], in = a.in_cnt[c];
-        if (out + in > kBigFill) fill_big_chunk(a, c, out, in);
+        const int32_t h = V.ndead[c] + a.out_cnt[c];
+        const int64_t slot = r < h ? base + a.hole[base + h - 1 - r]
+                                   : base + V.cnt[c] + (r - h);
+        place_mover(V, slot, a.mv, m);
     }
 }
 
-// Full re-bin, first pass: particles per destination chunk.
+// Records the full re-bin places: the staged injections, or the movers the
+// step recorded (all of them unless the mover list overflowed; those it
+// could not record stayed in place).
+template <class T>
+__device__ __forceinline__ int64_t records(const RebinArgs<T> &a)
+{
+    const int64_t nm = a.flags[nmov_slot(a.epoch)];
+    return a.npend + (nm < a.mcap ? nm : a.mcap);
+}
+
+// Full re-bin, first pass: particles per destination chunk, from the
+// occupied slots (holes skipped) and the records.
 template <class T>
 __device__ void rekey_count(const RebinArgs<T> &a)
 {
@@ -1170,27 +1149,44 @@ __device__ void rekey_count(const RebinArgs<T> &a)
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            const int64_t cn = chunk_after(a.p, c, x, y, z);
+            const bool live = occupied(x, V.d[q]);
+            const int64_t cn = live ? chunk_after(a.p, c, x, y, z) : -1;
             // one atomic per wave for the lanes that stay in chunk c
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
                 if (__lane_id() == __ffsll((unsigned long long)stay) - 1)
                     atomicAdd(&a.new_cnt[c], __popcll(stay));
-            } else {
+            } else if (live) {
                 atomicAdd(&a.new_cnt[cn], 1);
             }
         }
     }
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < a.npend;
+    const int64_t nr = records(a);
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nr;
          m += (int64_t)gridDim.x * blockDim.x)
         atomicAdd(&a.new_cnt[a.mv.dest[m]], 1);
 }
 
 template <class T>
-__global__ void __launch_bounds__(kFillBlock) k_fill_or_count(RebinArgs<T> a)
+__global__ void __launch_bounds__(kArriveBlock) k_arrive_or_count(RebinArgs<T> a)
 {
     if (full_rebin(a.flags, a.epoch)) rekey_count(a);
-    else fill_chunks(a);
+    else arrive(a);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_counts(View<T> V, const int32_t *out_cnt,
+                                                const int32_t *in_cnt, int64_t C, int32_t *flags,
+                                                int32_t epoch)
+{
+    if (full_rebin(flags, epoch)) return;
+    int32_t dead = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += (int64_t)gridDim.x * blockDim.x)
+        dead += count_chunk(V, out_cnt, in_cnt, c);
+    int32_t total;
+    block_excl_scan<int32_t>(dead, total);
+    if (threadIdx.x == 0 && total) atomicAdd(&flags[F_DEAD], total);
 }
 
 // Full re-bin, second pass: scatter into the second store.
@@ -1207,30 +1203,33 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(RebinArgs<T> a)
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
-            const int64_t cn = chunk_after(a.p, c, x, y, z);
-            int64_t dst;
+            const T dd = V.d[q];
+            const bool live = occupied(x, dd);      // holes are dropped
+            const int64_t cn = live ? chunk_after(a.p, c, x, y, z) : -1;
+            int64_t dst = -1;
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
                 const int leader = __ffsll((unsigned long long)stay) - 1;
                 int32_t b = 0;
                 if (__lane_id() == leader) b = atomicAdd(&a.cursor[c], __popcll(stay));
-                b = __shfl(b, leader);
+                b = __shfl(b, leader, 64);
                 dst = a.nbase[c] + b + __popcll(stay & lanes_below_mask());
-            } else {
+            } else if (live) {
                 dst = a.nbase[cn] + atomicAdd(&a.cursor[cn], 1);
             }
+            if (!live) continue;
             W.ox[dst] = x;
             W.oy[dst] = y;
             W.oz[dst] = z;
             W.vx[dst] = V.vx[q];
             W.vy[dst] = V.vy[q];
             W.vz[dst] = V.vz[q];
-            W.d[dst] = V.d[q];
-            const int32_t id = V.id[q];
-            W.id[dst] = id < 0 ? -1 - id : id;
+            W.d[dst] = dd;
+            W.id[dst] = V.id[q];
         }
     }
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < a.npend;
+    const int64_t nr = records(a);
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nr;
          m += (int64_t)gridDim.x * blockDim.x) {
         const int64_t cn = a.mv.dest[m];
         const int64_t dst = a.nbase[cn] + atomicAdd(&a.cursor[cn], 1);
@@ -1259,14 +1258,18 @@ __global__ void k_rekey_commit(RebinArgs<T> a, ItemArgs ia, int items_here)
     }
     for (int64_t c = g0; c < a.C; c += gs) {
         V.cnt[c] = a.new_cnt[c];
+        V.ndead[c] = 0;
         V.base[c] = a.nbase[c];
         V.room[c] = a.nroom[c];
         a.new_cnt[c] = 0;   // ready for the next full re-bin
         a.cursor[c] = 0;
         if (items_here) write_items(ia, c);
     }
-    if (items_here && g0 == 0) finish_flags(ia);
-    if (g0 == 0) a.flags[F_REPACKS] += 1;
+    if (g0 == 0) {
+        a.flags[F_DEAD] = 0;
+        if (items_here) finish_flags(ia);
+        a.flags[F_REPACKS] += 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1327,6 +1330,7 @@ __global__ void __launch_bounds__(256) k_get_particles(View<T> V, const int32_t 
         const int64_t s0 = V.base[c] + seg * kSeg;
         const int64_t s1 = min(s0 + (int64_t)kSeg, V.base[c] + (int64_t)V.cnt[c]);
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
+            if (!occupied(V.ox[q], V.d[q])) continue;   // a hole
             const int64_t k = V.id[q];
             if (k < 0 || k >= count) continue;  // never in a consistent store
             const T o[3] = {V.ox[q], V.oy[q], V.oz[q]};
@@ -1398,17 +1402,20 @@ __global__ void k_rotate(const T *u0, T *u, int64_t ncell, double cs, double sn)
     }
 }
 
-// checkpoint copy of the store (all slots) and its layout
+// checkpoint copy of the store (all slots), its hole lists and its layout
 template <class T>
-__global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, SnapLayout L,
-                           int32_t *items, const int32_t *nitems, int64_t max_items, int restore)
+__global__ void k_snapshot(View<T> V, int32_t *hole, int64_t slots, int64_t C, char *buf,
+                           SnapLayout L, int32_t *items, const int32_t *nitems, int64_t max_items,
+                           int restore)
 {
     T *arr[7] = {V.ox, V.oy, V.oz, V.vx, V.vy, V.vz, V.d};
     T *sT = reinterpret_cast<T *>(buf + L.state);
     int32_t *sid = reinterpret_cast<int32_t *>(buf + L.id);
+    int32_t *shole = reinterpret_cast<int32_t *>(buf + L.hole);
     int64_t *sbase = reinterpret_cast<int64_t *>(buf + L.base);
     int32_t *sroom = reinterpret_cast<int32_t *>(buf + L.room);
     int32_t *scnt = reinterpret_cast<int32_t *>(buf + L.cnt);
+    int32_t *sndead = reinterpret_cast<int32_t *>(buf + L.ndead);
     int32_t *sitems = reinterpret_cast<int32_t *>(buf + L.items);
     int32_t *snitems = reinterpret_cast<int32_t *>(buf + L.nitems);
     const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1424,9 +1431,11 @@ __global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, SnapL
         if (restore) {
             for (int a = 0; a < 7; ++a) arr[a][q] = sT[a * slots + q];
             V.id[q] = sid[q];
+            hole[q] = shole[q];
         } else {
             for (int a = 0; a < 7; ++a) sT[a * slots + q] = arr[a][q];
             sid[q] = V.id[q];
+            shole[q] = hole[q];
         }
     }
     for (int64_t c = g0; c < C; c += gs) {
@@ -1434,10 +1443,12 @@ __global__ void k_snapshot(View<T> V, int64_t slots, int64_t C, char *buf, SnapL
             V.base[c] = sbase[c];
             V.room[c] = sroom[c];
             V.cnt[c] = scnt[c];
+            V.ndead[c] = sndead[c];
         } else {
             sbase[c] = V.base[c];
             sroom[c] = V.room[c];
             scnt[c] = V.cnt[c];
+            sndead[c] = V.ndead[c];
         }
     }
 }
@@ -1467,6 +1478,7 @@ View<T> view_of(st_ctx *c, int b)
     v.base = c->base;
     v.room = c->room;
     v.cnt = c->cnt;
+    v.ndead = c->ndead;
     return v;
 }
 
@@ -1476,7 +1488,15 @@ Movers<T> movers_of(st_ctx *c)
     Movers<T> m;
     m.rec = (MoverRec<T> *)c->mov[0];
     m.dest = (int32_t *)c->mov[1];
+    m.rank = (int32_t *)c->mov[2];
     return m;
+}
+
+// more holes than this force a full re-bin (a sixteenth of the particles)
+inline int32_t dead_limit(const st_ctx *c)
+{
+    const int64_t v = c->count / 16 + 1024;
+    return (int32_t)(v < 0x7fffffff ? v : 0x7fffffff);
 }
 
 template <class F>
@@ -1528,12 +1548,12 @@ RebinArgs<T> rebin_args(st_ctx *c, int64_t npend)
     a.C = c->C;
     a.out_cnt = c->out_cnt;
     a.in_cnt = c->in_cnt;
-    a.inbox = c->inbox;
     a.hole = c->hole;
     a.items = c->items;
     a.nitems = c->flags + F_NITEMS;
     a.p = c->prm;
     a.npend = npend;
+    a.mcap = c->mcap;
     a.new_cnt = c->new_cnt;
     a.cursor = c->cursor;
     a.nbase = c->nbase;
@@ -1545,16 +1565,17 @@ RebinArgs<T> rebin_args(st_ctx *c, int64_t npend)
     return a;
 }
 
-// everything after the step kernel: fill or full re-bin, then the items
+// everything after the step kernel: arrivals or full re-bin, then the items
 template <class T>
 hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
 {
     const RebinArgs<T> a = rebin_args<T>(c, npend);
     const int64_t C = c->C;
-    // a wave per chunk for the fill; the count (rare) strides over the items
-    int64_t g = (C + kFillBlock / 64 - 1) / (kFillBlock / 64);
+    // a thread per mover for the arrivals (at most mcap of them); the count
+    // (rare) strides over the items
+    int64_t g = std::max<int64_t>((c->mcap + kArriveBlock - 1) / kArriveBlock, c->max_items);
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL((k_fill_or_count<T>), dim3(g), dim3(kFillBlock), 0, s, a);
+    hipLaunchKernelGGL((k_arrive_or_count<T>), dim3(g), dim3(kArriveBlock), 0, s, a);
     const int64_t total = c->count + npend;
     const RoomWeight rw{c->new_cnt, {c->prm.nc[0], c->prm.nc[1], c->prm.nc[2]}};
     const Rooms rooms{rw, c->slots - total - (int64_t)kAlign * C, 0, c->nroom};
@@ -1562,16 +1583,18 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
     // grids of at most 2048 workgroups (strided loops) keep that cheap
     const int64_t gs = c->max_items < 2048 ? c->max_items : 2048;
     ItemArgs ia{C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
-                c->epoch};
+                c->epoch, dead_limit(c)};
     if (C <= kScan1Max) {
-        // rooms (when due) and the next items in one workgroup
-        hipLaunchKernelGGL(k_layout1, dim3(1), dim3(1024), 0, s, rooms, c->nbase,
-                           Segments{c->cnt}, Segments{c->new_cnt}, ia, c->flags);
+        // counts, rooms (when due) and the next items in one workgroup
+        hipLaunchKernelGGL((k_layout1<T>), dim3(1), dim3(1024), 0, s, rooms, c->nbase,
+                           Segments{c->cnt}, Segments{c->new_cnt}, ia, a.V, c->flags);
         hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 2048)), dim3(256), 0, s,
                            a, ia, 1);
         return hipGetLastError();
     }
+    hipLaunchKernelGGL((k_counts<T>), dim3(grid_for(C)), dim3(256), 0, s, a.V, c->out_cnt,
+                       c->in_cnt, C, c->flags, c->epoch);
     hipLaunchKernelGGL(k_room_denom, dim3((C + kScanBlock - 1) / kScanBlock), dim3(256), 0, s, rw,
                        C, c->room_denom, c->flags, c->epoch);
     hipError_t e = scan<int64_t>(RoomsDev{rooms, c->room_denom}, C, c->nbase, c->scan_tmp,
@@ -1593,7 +1616,7 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
 hipError_t launch_items(st_ctx *c, hipStream_t s)
 {
     ItemArgs a{c->C, c->nseg, c->items, c->out_cnt, c->in_cnt, c->new_cnt, c->cursor, c->flags,
-               c->epoch};
+               c->epoch, dead_limit(c)};
     if (c->C <= kScan1Max) {
         hipLaunchKernelGGL(k_items1, dim3(1), dim3(1024), 0, s, Segments{c->cnt}, a);
         return hipGetLastError();
@@ -1609,6 +1632,7 @@ hipError_t launch_init(st_ctx *c, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->cnt, c->C, 0);
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->room, c->C, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(c->C)), dim3(256), 0, s, c->ndead, c->C, 0);
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(c->C + 1)), dim3(256), 0, s, c->base, c->C + 1,
                        (int64_t)0);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, c->flags, (int64_t)F_COUNT, 0);
@@ -1637,7 +1661,6 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         a.out_cnt = c->out_cnt;
         a.in_cnt = c->in_cnt;
         a.hole = c->hole;
-        a.inbox = c->inbox;
         a.flags = c->flags;
         a.deposit = deposit;
         a.epoch = c->epoch;
@@ -1746,6 +1769,27 @@ hipError_t launch_rotate_field(st_ctx *c, const void *u0, void *out, double cs, 
     });
 }
 
+// streaming reference: a plain copy with the particle state's access pattern
+// (one 16-byte non-temporal load and store per thread)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(1024) k_stream_copy(const f32x4 *src, f32x4 *dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s)
+{
+    const int64_t n = bytes / 16;
+    int64_t g = (n + 1023) / 1024;
+    if (g < 1) g = 1;
+    if (g > (1 << 20)) g = 1 << 20;
+    hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(1024), 0, s, (const f32x4 *)src,
+                       (f32x4 *)dst, n);
+    return hipGetLastError();
+}
+
 // extrapolator-corrector, elementwise over cells and components
 __global__ void k_ec(int64_t n, int kind, const double *S_last, double *S_prev, double *E_prev,
                      double *applied)
@@ -1798,7 +1842,7 @@ hipError_t launch_snapshot(st_ctx *c, void *dst, int restore, hipStream_t s)
     hipError_t e = dispatch(c, [&](auto t, auto) -> hipError_t {
         using T = decltype(t);
         hipLaunchKernelGGL((k_snapshot<T>), dim3(grid_for(c->slots, 16384)), dim3(256), 0, s,
-                           view_of<T>(c, 0), c->slots, c->C, (char *)dst, L, c->items,
+                           view_of<T>(c, 0), c->hole, c->slots, c->C, (char *)dst, L, c->items,
                            c->flags + F_NITEMS, c->max_items, restore);
         return hipGetLastError();
     });

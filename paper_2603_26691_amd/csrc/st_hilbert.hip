@@ -147,7 +147,8 @@ __global__ void __launch_bounds__(256) k_bbox(BoxArgs<T> a)
             const int64_t q = q0 + threadIdx.x;
             int64_t part = -1;
             double xg[3] = {0.0, 0.0, 0.0};
-            if (q < s1) {
+            // a hole has a -1 offset (binary32) or a negated diameter (binary64)
+            if (q < s1 && a.V.ox[q] >= T(0) && a.V.d[q] > T(0)) {
                 const int64_t id = a.V.id[q];
                 if (id >= a.id0 && (id - a.id0) / a.per_part < a.nparts) {
                     part = (id - a.id0) / a.per_part;
@@ -198,6 +199,7 @@ View<T> store_view(st_ctx *c)
     v.base = c->base;
     v.room = c->room;
     v.cnt = c->cnt;
+    v.ndead = c->ndead;
     return v;
 }
 

@@ -2,8 +2,10 @@
 //
 // Particle store: structure of arrays, kept sorted by chunk (a cube of
 // E^3 cells, E = chunk_edge).  Chunk c owns the slot range
-// [base[c], base[c] + room[c]); its cnt[c] live particles sit densely at
-// the start of that range.  Positions are stored as chunk-local offsets in
+// [base[c], base[c] + room[c]); its particles sit in the first cnt[c] slots
+// of that range, among ndead[c] holes: slots a particle left whose diameter
+// is NaN, listed (relative to base[c]) at hole[base[c] .. base[c] +
+// ndead[c]).  Arrivals fill holes first.  Positions are stored as chunk-local offsets in
 // cell units, xi in [0, E) per axis; the chunk origin is exact (the chunk
 // index times E cells).  Kernels get the store's pointers as arguments (so
 // every access is a global-memory instruction); a full re-bin scatters into
@@ -25,6 +27,12 @@ constexpr int kSeg = 16384;       // max particles per step work item
 constexpr int kSlackMin = 32;     // spare-slot weight per chunk in the room formula
 constexpr int kMoverStage = 512;  // movers per workgroup staged in LDS
 constexpr int kAlign = 4;         // chunk rooms are whole multiples of this
+// The state arrays are streamed together at equal slot indices; array k of
+// store b starts (8 b + k) kStagger bytes into its allocation, so that equal
+// indices of different arrays do not fall on the same HBM channels (aligned
+// starts measured 14 % slower on the 1.4e9-particle plume workload; staggers
+// of 1 KiB to 17 KiB all remove it, 256 B does not).
+constexpr size_t kStagger = 4096 + 256;
 // partitions st_bounding_boxes_noalloc can take (its fixed device scratch)
 constexpr int64_t kNoAllocMaxParts = 65536;
 
@@ -32,11 +40,13 @@ template <class T>
 struct View {
     T *ox, *oy, *oz;   // chunk-local offsets [cells]
     T *vx, *vy, *vz;   // velocity [m/s]
-    T *d;              // diameter [m]
-    int32_t *id;       // particle id; -1-id marks a slot vacated this step
+    T *d;              // diameter [m]; -d marks a slot its particle left this
+                       // step (the particle's state is still in place), NaN a hole
+    int32_t *id;       // particle id
     int64_t *base;     // [C] first slot of the chunk
     int32_t *room;     // [C] slots owned by the chunk
-    int32_t *cnt;      // [C] live particles of the chunk
+    int32_t *cnt;      // [C] slots in use: particles and holes
+    int32_t *ndead;    // [C] holes among them
 };
 
 // One particle in flight between chunks (also the staging area of
@@ -54,6 +64,7 @@ template <class T>
 struct Movers {
     MoverRec<T> *rec;
     int32_t *dest;     // destination chunk
+    int32_t *rank;     // rank among the destination's arrivals of the step
 };
 
 // Scalars of the mesh and material used by the kernels.
@@ -78,8 +89,9 @@ struct Params {
 // Flags and counters on the device (one int32 each).  F_OVERFLOW and
 // F_FORCE hold the tag (epoch) of the step or flush that raised them; the
 // movers of a step are counted in F_NMOV or F_NMOV_ODD by the tag's parity.
+// F_DEAD counts the holes of the store after the last arrivals.
 enum DevFlag { F_OVERFLOW = 0, F_NMOV = 1, F_NITEMS = 2, F_FORCE = 3, F_BADINPUT = 4,
-               F_REPACKS = 5, F_LASTMOV = 6, F_NMOV_ODD = 7, F_COUNT = 8 };
+               F_REPACKS = 5, F_LASTMOV = 6, F_NMOV_ODD = 7, F_DEAD = 8, F_COUNT = 9 };
 
 struct TapeStep {
     const void *u;     // field of the step (borrowed)
@@ -92,10 +104,10 @@ struct Snapshot {      // particle store and layout at a checkpoint
 };
 
 // Byte offsets inside a snapshot: the 7 state arrays ([7][slots] of the
-// state scalar), ids, the chunk layout (base, room, cnt) and the work items
-// of that layout with their count.
+// state scalar), ids, the hole lists, the chunk layout (base, room, cnt,
+// ndead) and the work items of that layout with their count.
 struct SnapLayout {
-    size_t state, id, base, room, cnt, items, nitems, bytes;
+    size_t state, id, hole, base, room, cnt, ndead, items, nitems, bytes;
 };
 
 inline SnapLayout snap_layout(int64_t slots, size_t tsize, int64_t C, int64_t max_items)
@@ -104,10 +116,12 @@ inline SnapLayout snap_layout(int64_t slots, size_t tsize, int64_t C, int64_t ma
     SnapLayout l;
     l.state = 0;
     l.id = 7 * (size_t)slots * tsize;
-    l.base = up8(l.id + (size_t)slots * 4);
+    l.hole = l.id + (size_t)slots * 4;
+    l.base = up8(l.hole + (size_t)slots * 4);
     l.room = l.base + (size_t)C * 8;
     l.cnt = l.room + (size_t)C * 4;
-    l.items = up8(l.cnt + (size_t)C * 4);
+    l.ndead = l.cnt + (size_t)C * 4;
+    l.items = up8(l.ndead + (size_t)C * 4);
     l.nitems = l.items + (size_t)max_items * 8;
     l.bytes = up8(l.nitems + 4);
     return l;
@@ -134,17 +148,18 @@ struct st_ctx {
 
     // device memory
     void *store[2][8] = {};    // SoA arrays: [0] the store, [1] re-bin target
+    void *store_raw[2][8] = {};  // their allocations (the arrays start past a stagger)
     int64_t *base = nullptr;   // [C+1] layout of the store
     int32_t *room = nullptr;   // [C]
     int32_t *cnt = nullptr;    // [C]
-    void *mov[2] = {};         // Movers: records, destination chunks
+    int32_t *ndead = nullptr;  // [C]
+    void *mov[3] = {};         // Movers: records, destination chunks, ranks
     int32_t *out_cnt = nullptr, *in_cnt = nullptr;
     int32_t *cursor = nullptr;     // [C] scatter cursors of the full re-bin
     int32_t *new_cnt = nullptr;    // [C]
     int64_t *nbase = nullptr;      // [C+1] first slots of the re-binned layout
     int32_t *nroom = nullptr;      // [C]   rooms of the re-binned layout
-    int32_t *hole = nullptr;       // [slots]
-    int32_t *inbox = nullptr;      // [slots] arrivals of chunk c at base[c] + rank
+    int32_t *hole = nullptr;       // [slots] holes of chunk c from base[c]
     int32_t *items = nullptr;      // [max_items][2]
     int32_t *nseg = nullptr;       // [C+1] offsets of the work items per chunk
     int64_t *scan_tmp = nullptr;   // block partials of the scans
@@ -205,6 +220,7 @@ hipError_t launch_bounding_boxes(st_ctx *c, int64_t id0, int64_t per_part, int64
 // current; once per device, later calls return at once); noalloc_scratch
 // returns that address, or an error if it was never taken.
 hipError_t noalloc_scratch_init(int device);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t bytes, hipStream_t s);
 hipError_t noalloc_scratch(int device, double **ptr);
 
 }  // namespace st

@@ -247,11 +247,12 @@ class Tracker:
         N.check(N.lib().st_ec_reset(self.ctx, _stream()), self.ctx)
 
     def stats(self):
-        m, r, p, s, i = (ctypes.c_int64() for _ in range(5))
+        m, r, p, s, i, h = (ctypes.c_int64() for _ in range(6))
         N.check(N.lib().st_stats(self.ctx, ctypes.byref(m), ctypes.byref(r), ctypes.byref(p),
-                                 ctypes.byref(s), ctypes.byref(i), _stream()), self.ctx)
+                                 ctypes.byref(s), ctypes.byref(i), ctypes.byref(h), _stream()),
+                self.ctx)
         return {"movers": m.value, "repacks": r.value, "particles": p.value, "slots": s.value,
-                "items": i.value}
+                "items": i.value, "holes": h.value}
 
     def timing(self, enable):
         """Starts (True) or stops (False) timing the step kernel; returns
