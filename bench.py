@@ -394,8 +394,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+adjoint leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--only", default=None,
-                    help="run one forward leg alone: plume512, plume256, plume256_fp64, "
-                         "tg128 (for profiling)")
+                    help="run one leg alone: plume512, plume256, plume256_fp64, tg128, "
+                         "adjoint (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the streaming copy of MIB MiB three times (the reference "
                          "for scaling hardware byte counters) and exit")
@@ -423,6 +423,9 @@ def main():
                                            ctypes.c_void_p(b.data_ptr()), 4 * n, s))
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.only == "adjoint":
+        print(json.dumps(leg_adjoint(pkg, torch, np, synth)), flush=True)
         return
     if args.only:
         name = args.only.replace("_fp64", "")

@@ -71,7 +71,10 @@ typedef enum {
      * chunk-local offsets (the chunk origin is exact, implied by the chunk
      * index); impulses, source accumulation and totals in binary64 */
     ST_FORM_FP32_LOCAL = 1,
-    /* everything in binary32, sources included */
+    /* everything in binary32, sources included; positions stored as
+     * coordinates in metres, a particle's cell taken from the binary32
+     * product x * fl32(n / L) (clamped to [0, n)).  Steps cannot be taped
+     * in this form. */
     ST_FORM_FP32 = 2
 } st_form;
 
@@ -140,7 +143,8 @@ st_status st_count(const st_ctx *ctx, int64_t *n);
  * tape != 0 records the step for st_backward: the field pointer is then
  * borrowed until st_backward or st_tape_clear; a checkpoint of the
  * particle state is kept every `tape` sub-steps (the value of the first
- * taped call fixes the interval).  dt must be finite and > 0, nsub >= 1. */
+ * taped call fixes the interval; ST_ERR_INVALID in the form
+ * ST_FORM_FP32).  dt must be finite and > 0, nsub >= 1. */
 st_status st_step(st_ctx *ctx, const void *u_cells, double dt, int32_t nsub,
                   int32_t tape, void *hip_stream);
 

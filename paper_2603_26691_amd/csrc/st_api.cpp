@@ -133,6 +133,11 @@ st_status st_create_mesh(const st_mesh_desc *desc, int device, st_ctx **out)
         p.inv_h[a] = 1.0 / p.h[a];
         p.g[a] = d.g[a];
     }
+    p.global = d.form == ST_FORM_FP32 ? 1 : 0;
+    for (int a = 0; a < 3; ++a) {
+        p.inv_hf[a] = (float)(d.n[a] / d.L[a]);
+        p.Lf[a] = (float)d.L[a];
+    }
     p.C = (int64_t)p.nc[0] * p.nc[1] * p.nc[2];
     p.inv_V = 1.0 / (p.h[0] * p.h[1] * p.h[2]);
     p.tau_coef = d.rho_p / (18.0 * d.mu_f);
@@ -314,6 +319,9 @@ st_status st_step(st_ctx *c, const void *u_cells, double dt, int32_t nsub, int32
         if (!(isfinite(dt) && dt > 0)) return fail(c, ST_ERR_INVALID, "st_step: dt must be finite and > 0");
         if (nsub < 1) return fail(c, ST_ERR_INVALID, "st_step: nsub must be >= 1");
         if (tape < 0) return fail(c, ST_ERR_INVALID, "st_step: tape must be >= 0");
+        if (tape > 0 && c->form == ST_FORM_FP32)
+            return fail(c, ST_ERR_INVALID,
+                        "st_step: taped steps need the FP64 or FP32 chunk-local form");
         if (tape > 0 && c->tape.empty() && c->tape_every == 0) c->tape_every = tape;
         if (tape == 0 && !c->tape.empty())
             return fail(c, ST_ERR_STATE, "st_step: untaped step while a tape is recorded");

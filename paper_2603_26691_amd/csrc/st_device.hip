@@ -13,18 +13,20 @@
 //             one arrival count per neighbouring chunk), and flush the
 //             accumulator with one read-modify-write (or one atomic, for
 //             chunks split over several items) per cell.  A mover's slot
-//             becomes a hole of its chunk (its diameter negated, its state
-//             left in place); its record carries its destination and its
-//             rank among the destination's arrivals.  Arrivals that do not
-//             fit the destination's free slots force the full re-bin;
+//             becomes a hole of its chunk (binary32: a -1 offset, written by
+//             the step's own store; binary64: its diameter negated, its
+//             state left in place) and goes onto the chunk's hole list; its
+//             record carries its destination and its rank among the
+//             destination's arrivals.  Arrivals that do not fit the
+//             destination's free slots force the full re-bin;
 //   arrive    one thread per mover: each arrival takes a hole of its
 //             destination (the newest first) or, when there are none left,
-//             the next slot past the destination's last (or, when a full
-//             re-bin is due, the re-keyed counts);
-//   counts    one wave per chunk: the new slot and hole counts; holes no
-//             arrival took get a NaN diameter and are skipped by every
-//             kernel until the next full re-bin (forced once they exceed a
-//             sixteenth of the particles);
+//             the next slot past the destination's last (when a full re-bin
+//             is due, nothing: the re-bin takes the movers from their
+//             records);
+//   counts    one thread per chunk: the new slot and hole counts; holes no
+//             arrival took are skipped by every kernel until the next full
+//             re-bin (forced once they exceed a sixteenth of the particles);
 //   layout    work items of the next step from the counts, the reset of the
 //             counters, and, when a full re-bin is due, the rooms and bases
 //             of its layout (one workgroup; it also takes the counts step
@@ -346,6 +348,29 @@ __device__ __forceinline__ int64_t chunk_after(const Params &p, int64_t c, T &ox
                        wrapi(cz + kz, p.nc[2]));
 }
 
+// FP32-everywhere form: the cell of a binary32 coordinate in metres along one
+// axis, from the rounded binary32 product x n / L (a rounding that reaches n
+// stays in the last cell).  Every kernel takes a particle's cell and chunk
+// from this one product, so they agree on them.
+__device__ __forceinline__ float gprod(float x, float inv_h) { return __fmul_rn(x, inv_h); }
+__device__ __forceinline__ int gcell(float x, float inv_h, int n)
+{
+    const int c = (int)floorf(gprod(x, inv_h));
+    return min(max(c, 0), n - 1);
+}
+
+// The chunk of a stored position: chunk-local offsets re-based from chunk c
+// (left re-based), or binary32 coordinates in metres (left as they are).
+template <class T>
+__device__ __forceinline__ int64_t chunk_of_stored(const Params &p, int64_t c, T &x, T &y, T &z)
+{
+    if (p.global)
+        return chunk_index(p, gcell((float)x, p.inv_hf[0], p.n[0]) / p.E,
+                           gcell((float)y, p.inv_hf[1], p.n[1]) / p.E,
+                           gcell((float)z, p.inv_hf[2], p.n[2]) / p.E);
+    return chunk_after(p, c, x, y, z);
+}
+
 // ---------------------------------------------------------------------------
 // work items of the next step, and the reset of the per-step counters
 // ---------------------------------------------------------------------------
@@ -594,7 +619,7 @@ __device__ __forceinline__ bool emit_mover(const StepArgs<T, A> &a, int64_t c, i
 {
     const View<T> &V = a.V;
     const int32_t id = V.id[q];
-    const int64_t cn = chunk_after(a.p, c, x, y, z);
+    const int64_t cn = chunk_of_stored(a.p, c, x, y, z);
     a.hole[base + hpos] = (int32_t)(q - base);
     if (m >= a.mcap) {
         a.flags[F_OVERFLOW] = a.epoch;
@@ -721,6 +746,10 @@ __global__ void __launch_bounds__(kBlock)
 
     const T dt = a.dt;
     const T fe = T(E), inv_e = T(1) / T(E);
+    // FP32-everywhere form: positions in binary32 metres, the cell arithmetic
+    // in binary32 (the chunk origin in cells is exact)
+    constexpr bool GLOBAL = sizeof(A) == 4;
+    const T org[3] = {T(cx * E), T(cy * E), T(cz * E)};
     for (; gi < ngroups; gi += kBlock) {
         T Xn[G], Yn[G], Zn[G], UXn[G], UYn[G], UZn[G], DDn[G];
         if (gi + kBlock < ngroups) load_group(gi + kBlock, Xn, Yn, Zn, UXn, UYn, UZn, DDn);
@@ -731,7 +760,12 @@ __global__ void __launch_bounds__(kBlock)
         for (int k = 0; k < G; ++k) {
             // slots past the run and holes hold no particle
             const bool valid = (int)o + k < nq && occupied(X[k], DD[k]);
-            const T xi[3] = {X[k], Y[k], Z[k]};
+            T xi[3] = {X[k], Y[k], Z[k]};   // cell units from the chunk origin
+            if constexpr (GLOBAL) {
+                xi[0] = gprod(X[k], p.inv_hf[0]) - org[0];
+                xi[1] = gprod(Y[k], p.inv_hf[1]) - org[1];
+                xi[2] = gprod(Z[k], p.inv_hf[2]) - org[2];
+            }
             const T up[3] = {UX[k], UY[k], UZ[k]};
             const T dp = DD[k];
 
@@ -804,9 +838,30 @@ __global__ void __launch_bounds__(kBlock)
             // relocate: a particle whose new offset left [0, E) on some axis
             // crossed into another chunk; it keeps the un-rebased offsets
             // (relative to this chunk) until it is emitted and re-based.  A
-            // particle that stays needs no re-basing.
-            const bool mover = xn[0] < T(0) || xn[0] >= fe || xn[1] < T(0) || xn[1] >= fe ||
-                               xn[2] < T(0) || xn[2] >= fe;
+            // particle that stays needs no re-basing.  FP32-everywhere form:
+            // the new position in metres, wrapped, and its chunk from its cells
+            bool mover;
+            int gk[3] = {0, 0, 0};   // FP32-everywhere: chunk steps per axis
+            if constexpr (GLOBAL) {
+                const T xg[3] = {X[k], Y[k], Z[k]};
+                for (int ax = 0; ax < 3; ++ax) {
+                    T v = xg[ax] + upn[ax] * dt;
+                    if (v >= p.Lf[ax]) v -= p.Lf[ax];
+                    if (v < T(0)) v += p.Lf[ax];
+                    if (v >= p.Lf[ax]) v = T(0);
+                    xn[ax] = v;
+                    const int cc = ax == 0 ? cx : ax == 1 ? cy : cz;
+                    int dk = gcell(v, p.inv_hf[ax], p.n[ax]) / E - cc;
+                    // the shorter way round the periodic domain
+                    if (dk > 1 && dk == p.nc[ax] - 1) dk = -1;
+                    if (dk < -1 && dk == 1 - p.nc[ax]) dk = 1;
+                    gk[ax] = dk;
+                }
+                mover = (gk[0] | gk[1] | gk[2]) != 0;
+            } else {
+                mover = xn[0] < T(0) || xn[0] >= fe || xn[1] < T(0) || xn[1] >= fe ||
+                        xn[2] < T(0) || xn[2] >= fe;
+            }
             if (valid) {   // a hole keeps what it holds (binary32: the -1 offset)
                 X[k] = xn[0];
                 Y[k] = xn[1];
@@ -817,10 +872,13 @@ __global__ void __launch_bounds__(kBlock)
             }
             if (valid && mover) {
                 movers |= 1u << k;
-                T tx = xn[0], ty = xn[1], tz = xn[2];
-                const int kx = rebase(tx, fe, inv_e);
-                const int ky = rebase(ty, fe, inv_e);
-                const int kz = rebase(tz, fe, inv_e);
+                int kx = gk[0], ky = gk[1], kz = gk[2];
+                if constexpr (!GLOBAL) {
+                    T tx = xn[0], ty = xn[1], tz = xn[2];
+                    kx = rebase(tx, fe, inv_e);
+                    ky = rebase(ty, fe, inv_e);
+                    kz = rebase(tz, fe, inv_e);
+                }
                 const int dir = (abs(kx) <= 1 && abs(ky) <= 1 && abs(kz) <= 1)
                                     ? (kx + 1) + 3 * (ky + 1) + 9 * (kz + 1) : 27;
                 dirs |= (uint32_t)dir << (kDirBits * k);
@@ -1023,11 +1081,10 @@ __global__ void __launch_bounds__(kBlock)
         const int dir = (w >> kSlotBits) & ((1 << kDirBits) - 1);
         const int rank = w >> (kSlotBits + kDirBits);
         const int64_t m = (int64_t)mbase_sh + doff[dir] + rank;
-        // re-base the offsets into the destination chunk
+        // re-base the offsets into the destination chunk (FP32-everywhere
+        // form: positions in metres stay as they are)
         T rx = mx[u], ry = my[u], rz = mz[u];
-        const int kx = rebase(rx, fe, inv_e);
-        const int ky = rebase(ry, fe, inv_e);
-        const int kz = rebase(rz, fe, inv_e);
+        const int64_t cfar = chunk_of_stored(p, c, rx, ry, rz);
         int64_t dest;
         int32_t r;
         if (dir < 27) {   // within the direction's reservation
@@ -1036,8 +1093,7 @@ __global__ void __launch_bounds__(kBlock)
                                wrapi(cz + dir / 9 - 1, p.nc[2]));
             r = dbase[dir] + rank;
         } else {          // farther than one chunk: a reservation of its own
-            dest = chunk_index(p, wrapi(cx + kx, p.nc[0]), wrapi(cy + ky, p.nc[1]),
-                               wrapi(cz + kz, p.nc[2]));
+            dest = cfar;
             r = atomicAdd(&a.in_cnt[dest], 1);
             if (r >= free_slots(V, dest)) a.flags[F_OVERFLOW] = a.epoch;
         }
@@ -1150,7 +1206,7 @@ __device__ void rekey_count(const RebinArgs<T> &a)
         for (int64_t q = s0 + threadIdx.x; q < s1; q += blockDim.x) {
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
             const bool live = occupied(x, V.d[q]);
-            const int64_t cn = live ? chunk_after(a.p, c, x, y, z) : -1;
+            const int64_t cn = live ? chunk_of_stored(a.p, c, x, y, z) : -1;
             // one atomic per wave for the lanes that stay in chunk c
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
@@ -1205,7 +1261,7 @@ __global__ void __launch_bounds__(256) k_rekey_scatter(RebinArgs<T> a)
             T x = V.ox[q], y = V.oy[q], z = V.oz[q];
             const T dd = V.d[q];
             const bool live = occupied(x, dd);      // holes are dropped
-            const int64_t cn = live ? chunk_after(a.p, c, x, y, z) : -1;
+            const int64_t cn = live ? chunk_of_stored(a.p, c, x, y, z) : -1;
             int64_t dst = -1;
             const uint64_t stay = __ballot(cn == c);
             if (cn == c) {
@@ -1290,6 +1346,13 @@ __global__ void k_stage(int64_t n, const double *x, const double *up, const doub
             // periodic image in [0, L)
             xa = xa - floor(xa / p.L[a]) * p.L[a];
             if (xa >= p.L[a] || xa < 0.0) xa = 0.0;
+            if (p.global) {   // binary32 metres; its cell from the binary32 product
+                float xf = (float)xa;
+                if (xf >= p.Lf[a]) xf = 0.f;
+                ch[a] = gcell(xf, p.inv_hf[a], p.n[a]) / p.E;
+                loc[a] = (T)xf;
+                continue;
+            }
             double g = xa / p.h[a];                  // cell units
             int64_t ci = (int64_t)floor(g);
             if (ci >= p.n[a]) { g -= p.n[a]; ci -= p.n[a]; }
@@ -1337,9 +1400,15 @@ __global__ void __launch_bounds__(256) k_get_particles(View<T> V, const int32_t 
             const T v[3] = {V.vx[q], V.vy[q], V.vz[q]};
             for (int a = 0; a < 3; ++a) {
                 const double org = (double)(cc[a] * p.E);
-                if (x) x[3 * k + a] = (org + (double)o[a]) * p.h[a];
+                if (p.global) {   // binary32 metres
+                    if (x) x[3 * k + a] = (double)o[a];
+                    if (cell) cell[3 * k + a] = gcell((float)o[a], p.inv_hf[a], p.n[a]);
+                } else {
+                    if (x) x[3 * k + a] = (org + (double)o[a]) * p.h[a];
+                    if (cell)
+                        cell[3 * k + a] = (int32_t)(cc[a] * p.E + min(max((int)o[a], 0), p.E - 1));
+                }
                 if (up) up[3 * k + a] = (double)v[a];
-                if (cell) cell[3 * k + a] = (int32_t)(cc[a] * p.E + min(max((int)o[a], 0), p.E - 1));
             }
             if (d) d[k] = (double)V.d[q];
             if (id) id[k] = k;

@@ -153,8 +153,9 @@ __global__ void __launch_bounds__(256) k_bbox(BoxArgs<T> a)
                 if (id >= a.id0 && (id - a.id0) / a.per_part < a.nparts) {
                     part = (id - a.id0) / a.per_part;
                     const T o[3] = {a.V.ox[q], a.V.oy[q], a.V.oz[q]};
-                    for (int ax = 0; ax < 3; ++ax)
-                        xg[ax] = ((double)(cc[ax] * p.E) + (double)o[ax]) * p.h[ax];
+                    for (int ax = 0; ax < 3; ++ax)   // binary32 metres in the FP32-everywhere form
+                        xg[ax] = p.global ? (double)o[ax]
+                                          : ((double)(cc[ax] * p.E) + (double)o[ax]) * p.h[ax];
                 }
             }
             const uint64_t has = __ballot(part >= 0);

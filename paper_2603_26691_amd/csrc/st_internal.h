@@ -3,11 +3,14 @@
 // Particle store: structure of arrays, kept sorted by chunk (a cube of
 // E^3 cells, E = chunk_edge).  Chunk c owns the slot range
 // [base[c], base[c] + room[c]); its particles sit in the first cnt[c] slots
-// of that range, among ndead[c] holes: slots a particle left whose diameter
-// is NaN, listed (relative to base[c]) at hole[base[c] .. base[c] +
-// ndead[c]).  Arrivals fill holes first.  Positions are stored as chunk-local offsets in
-// cell units, xi in [0, E) per axis; the chunk origin is exact (the chunk
-// index times E cells).  Kernels get the store's pointers as arguments (so
+// of that range, among ndead[c] holes: slots a particle left (a -1 offset in
+// binary32, a negative diameter in binary64), listed (relative to base[c])
+// at hole[base[c] .. base[c] + ndead[c]).  Arrivals fill holes first.
+// Positions are stored as chunk-local offsets in cell units, xi in [0, E)
+// per axis; the chunk origin is exact (the chunk index times E cells).  The
+// FP32-everywhere form stores binary32 coordinates in metres instead, and
+// takes the cell from their binary32 product with n / L.  Kernels get the
+// store's pointers as arguments (so
 // every access is a global-memory instruction); a full re-bin scatters into
 // a second store and copies back.
 #pragma once
@@ -38,10 +41,10 @@ constexpr int64_t kNoAllocMaxParts = 65536;
 
 template <class T>
 struct View {
-    T *ox, *oy, *oz;   // chunk-local offsets [cells]
+    T *ox, *oy, *oz;   // chunk-local offsets [cells] (FP32-everywhere form: metres)
     T *vx, *vy, *vz;   // velocity [m/s]
-    T *d;              // diameter [m]; -d marks a slot its particle left this
-                       // step (the particle's state is still in place), NaN a hole
+    T *d;              // diameter [m]; binary64: -d marks a hole (the state
+                       // of the particle that left it is still in place)
     int32_t *id;       // particle id
     int64_t *base;     // [C] first slot of the chunk
     int32_t *room;     // [C] slots owned by the chunk
@@ -84,6 +87,12 @@ struct Params {
     double tau_coef;       // rho_p / (18 mu_f): tau = tau_coef d^2
     double mass_coef;      // w rho_p pi / 6:    m = mass_coef d^3
     double re_coef;        // rho_f / mu_f:      Re = re_coef d |u_f - u_p|
+    // FP32-everywhere form: positions are stored as binary32 coordinates in
+    // metres (global != 0); its cell arithmetic in binary32
+    float inv_hf[3];       // binary32 n / L per axis
+    float Lf[3];           // binary32 L per axis
+    int32_t global;
+    int32_t pad2_;
 };
 
 // Flags and counters on the device (one int32 each).  F_OVERFLOW and

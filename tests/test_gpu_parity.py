@@ -4,7 +4,8 @@ Lockstep: at every step the oracle takes the GPU's state (promoted exactly
 to binary64) and the field the GPU used, advances one step, and the GPU's
 next state, cells and per-cell sources are compared with it.  Cells must be
 bit-exact except for particles within 1e-6 cell widths of a face (excluded
-and counted).  Tolerances: positions (per L) and velocities (per 1 m/s)
+and counted; 2^-21 n cell widths for the FP32-everywhere form, whose cell
+arithmetic is binary32).  Tolerances: positions (per L) and velocities (per 1 m/s)
 1e-5 and per-cell sources 1e-6 of the largest cell for the FP32
 chunk-local form; near round-off for the FP64 form; the FP32-everywhere
 form (precision study) is held to 1e-4 on sources.
@@ -14,8 +15,8 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import (FORMS, fields, lockstep_check, min_image, oracle_mesh, state, tracker,
-                         workload, face_distance, sphere_mass, BAND)
+from gpu_helpers import (FORMS, band, fields, lockstep_check, min_image, oracle_mesh, state,
+                         tracker, workload, face_distance, sphere_mass, BAND)
 from oracle.oracle import load as load_oracle
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +39,7 @@ def _run_lockstep(orc, w, form, nsteps=4, interp=0, nsub=1, dt=None, drag="stoke
     t.inject(x, up, d)
     Udev, Uor = fields(w, form)
     out = lockstep_check(t, orc, oracle_mesh(w, interp, drag), Udev, Uor, dt or w.dt, nsteps,
-                         TOL[form], nsub=nsub)
+                         TOL[form], nsub=nsub, band_=band(form, w.n))
     print(form, w.name, out)
     t.close()
     return out
