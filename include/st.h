@@ -183,13 +183,16 @@ st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
  * fields, which are one tensor when every step used the same field) and
  * dL/dd (device, [count] binary64, by id; may be NULL when count is 0).
  * Checkpoints are restored and
- * the steps between them recomputed.  The tape is consumed.  ST_ERR_STATE
- * if nothing is taped. */
+ * the steps between them recomputed.  The tape is consumed; its checkpoint
+ * buffers and the call's workspace (about tape + 2 copies of the particle
+ * store plus 64 bytes per particle) stay allocated for the next taped run
+ * until st_tape_clear or st_destroy.  Returns when the results are written
+ * (the call synchronises hip_stream).  ST_ERR_STATE if nothing is taped. */
 st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,
                       double *dL_dd, void *hip_stream);
 
 /* Outside the paper (see st_backward).  Drops the tape without
- * differentiating. */
+ * differentiating, and releases the buffers st_backward keeps. */
 st_status st_tape_clear(st_ctx *ctx);
 
 /* Paper Sec. 2.3 (asynchronous coupling; the Eulerian and Lagrangian phases

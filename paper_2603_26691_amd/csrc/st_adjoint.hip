@@ -21,8 +21,9 @@
 // The cell c0 and the periodic wrap are piecewise constant (zero derivative).
 //
 // Checkpoints of the particle store are kept every `tape_every` taped steps;
-// each segment is recomputed from its checkpoint (deposit off), saving the
-// store and its layout before every step, and then reversed newest first.
+// each segment is recomputed from its checkpoint (deposit off), each step
+// saving the state it starts from, the ids and its layout as it streams
+// them, and then reversed newest first.
 // The per-particle adjoint state is kept by particle id, so the re-binning
 // between steps needs no special treatment.
 #include "st_internal.h"
@@ -54,8 +55,7 @@ struct AdjArgs {
     double dt;
 };
 
-// One workgroup of 256 threads per work item (wider workgroups, and more
-// workgroups over shorter runs, measured slower).
+// One workgroup of 512 threads per work item, two per CU.
 constexpr int kAdjBlock = 256;
 
 // Block-wide exclusive scan of one value per thread (kAdjBlock threads);
@@ -255,12 +255,13 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
             const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
             const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
-            const double tau = tau_s / f;
+            const double tau = p.drag == 1 ? tau_s / f : tau_s;
             const double mass = p.mass_coef * dp * dp * dp;
-            const double D = tau + dt;
+            const double invD = 1.0 / (tau + dt);
+            const double dtD = dt * invD, tauD = tau * invD;
             double upn[3];
             for (int ax = 0; ax < 3; ++ax)
-                upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) / D;
+                upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) * invD;
 
             // reverse
             const int cell = (cl[2] * E + cl[1]) * E + cl[0];
@@ -275,10 +276,11 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
                 const double Jbar = -lam[ax * E3 + cell] * inv_V;
                 const double wbar = ub[ax] + dt * xb[ax] + mass * Jbar;
                 mbar += Jbar * (upn[ax] - up[ax] - p.g[ax] * dt);
-                ufb[ax] = dt / D * wbar;
-                taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]) / D;
-                ub[ax] = -mass * Jbar + tau / D * wbar;
+                ufb[ax] = dtD * wbar;
+                taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]);
+                ub[ax] = -mass * Jbar + tauD * wbar;
             }
+            taubar *= invD;
             double Rebar = 0.0;
             if (Re > 0.0) {
                 Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
@@ -314,8 +316,7 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
                 rec[ax] = xb[ax];
                 rec[3 + ax] = ub[ax];
             }
-            rec[6] = lr[u][6] + taubar / f * 2.0 * tau_s / dp + Rebar * Re / dp +
-                     mbar * 3.0 * mass / dp;
+            rec[6] = lr[u][6] + (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
         }
         }
         if (!TRI) break;
@@ -497,15 +498,6 @@ hipError_t launch_adjoint_step(st_ctx *c, const AdjArgs<T> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-struct DevBuf {
-    void *p = nullptr;
-    DevBuf() = default;
-    DevBuf(const DevBuf &) = delete;
-    DevBuf &operator=(const DevBuf &) = delete;
-    ~DevBuf() { (void)hipFree(p); }
-    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 8); }
-};
-
 }  // namespace
 
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s)
@@ -519,26 +511,40 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     const int64_t E3 = (int64_t)c->prm.E * c->prm.E * c->prm.E;
     const size_t sbytes = snapshot_bytes(c);
 
-    DevBuf final_state, lamC, adj;
-    std::vector<DevBuf> steps((size_t)K);
-    hipError_t e = final_state.alloc(sbytes);
-    if (e == hipSuccess) e = lamC.alloc((size_t)c->C * 3 * E3 * 8);
-    if (e == hipSuccess) e = adj.alloc((size_t)P * 64);
-    for (int64_t k = 0; k < K && e == hipSuccess; ++k) e = steps[(size_t)k].alloc(sbytes);
-    if (e != hipSuccess) return e;
+    // one workspace, kept in the context for the next call: the state the
+    // forward run ended in, the saved states of one segment, dL/dS by chunk
+    // and the adjoint records
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t o_steps = up256(sbytes);
+    const size_t o_lam = o_steps + (size_t)K * up256(sbytes);
+    const size_t o_adj = o_lam + up256((size_t)c->C * 3 * E3 * 8);
+    const size_t ws_bytes = o_adj + (size_t)(P > 0 ? P : 1) * 64;
+    if (c->bwd_ws_bytes < ws_bytes) {
+        (void)hipFree(c->bwd_ws);
+        c->bwd_ws = nullptr;
+        c->bwd_ws_bytes = 0;
+        hipError_t e = hipMalloc(&c->bwd_ws, ws_bytes);
+        if (e != hipSuccess) return e;
+        c->bwd_ws_bytes = ws_bytes;
+    }
+    char *ws = (char *)c->bwd_ws;
+    void *final_state = ws;
+    auto step_buf = [&](int64_t k) -> void * { return ws + o_steps + (size_t)k * up256(sbytes); };
+    double *lamC = (double *)(ws + o_lam);
+    double *adj = (double *)(ws + o_adj);
 
-    // temporaries are freed on return: an error return first drains the stream
+    // an error return first drains the stream
     auto fail = [&](hipError_t err) {
         (void)hipStreamSynchronize(s);
         return err;
     };
     // keep the state the forward run ended in
-    e = launch_snapshot(c, final_state.p, 0, s);
+    hipError_t e = launch_snapshot(c, final_state, 0, s);
     if (e != hipSuccess) return fail(e);
     hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
-                       (double *)lamC.p);
+                       lamC);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, (double *)adj.p, 8 * P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, adj, 8 * P);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
 
@@ -546,33 +552,34 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
         const int64_t k0 = sg * K, k1 = std::min(k0 + K, ntape);
         e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
         if (e != hipSuccess) return fail(e);
-        // recompute the segment, saving the store before every step
+        // recompute the segment, each step saving what its reverse reads; the
+        // last step's start is the store itself
         for (int64_t k = k0; k < k1; ++k) {
-            e = launch_snapshot(c, steps[(size_t)(k - k0)].p, 0, s);
-            if (e == hipSuccess && k + 1 < k1)
-                e = launch_step(c, c->tape[(size_t)k].u, c->tape[(size_t)k].dt, 0, s);
+            void *save = step_buf(k - k0);
+            if (k + 1 < k1)
+                e = launch_step(c, c->tape[(size_t)k].u, c->tape[(size_t)k].dt, 0, s, save);
+            else
+                e = launch_snapshot(c, save, 0, s);
             if (e != hipSuccess) return fail(e);
         }
         // and reverse it, newest step first
         for (int64_t k = k1 - 1; k >= k0; --k) {
-            const char *snap = (const char *)steps[(size_t)(k - k0)].p;
+            const char *snap = (const char *)step_buf(k - k0);
             if (c->form == ST_FORM_FP64)
                 e = launch_adjoint_step<double>(
-                    c, adj_args<double>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
-                                        (double *)adj.p, dU), s);
+                    c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
             else
                 e = launch_adjoint_step<float>(
-                    c, adj_args<float>(c, snap, c->tape[(size_t)k], (const double *)lamC.p,
-                                       (double *)adj.p, dU), s);
+                    c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
             if (e != hipSuccess) return fail(e);
         }
     }
-    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)adj.p, P, dd);
+    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)adj, P, dd);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
-    e = launch_snapshot(c, final_state.p, 1, s);
+    e = launch_snapshot(c, final_state, 1, s);
     if (e != hipSuccess) return fail(e);
-    // the temporaries are freed when this returns: finish first
+    // the tape's buffers are handed back when this returns: finish first
     return hipStreamSynchronize(s);
 }
 

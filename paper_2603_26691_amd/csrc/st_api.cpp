@@ -56,6 +56,11 @@ void free_all(st_ctx *c)
     for (void *p : singles) (void)hipFree(p);
     for (auto &sn : c->snaps) (void)hipFree(sn.buf);
     c->snaps.clear();
+    for (auto &sn : c->spare) (void)hipFree(sn.buf);
+    c->spare.clear();
+    (void)hipFree(c->bwd_ws);
+    c->bwd_ws = nullptr;
+    c->bwd_ws_bytes = 0;
     for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     c->tev.clear();
     if (c->side) (void)hipStreamDestroy(c->side);
@@ -334,9 +339,14 @@ st_status st_step(st_ctx *c, const void *u_cells, double dt, int32_t nsub, int32
             if (tape > 0) {
                 if (c->tape.size() % (size_t)c->tape_every == 0) {
                     st::Snapshot sn;
-                    sn.bytes = st::snapshot_bytes(c);
-                    hipError_t e = hipMalloc(&sn.buf, sn.bytes);
-                    if (e != hipSuccess) return fail(c, ST_ERR_OOM, "st_step: checkpoint");
+                    if (!c->spare.empty()) {   // a buffer of a consumed tape
+                        sn = c->spare.back();
+                        c->spare.pop_back();
+                    } else {
+                        sn.bytes = st::snapshot_bytes(c);
+                        hipError_t e = hipMalloc(&sn.buf, sn.bytes);
+                        if (e != hipSuccess) return fail(c, ST_ERR_OOM, "st_step: checkpoint");
+                    }
                     c->snaps.push_back(sn);
                     ST_HIP(st::launch_snapshot(c, sn.buf, 0, s));
                 }
@@ -407,15 +417,36 @@ st_status st_get_particles(st_ctx *c, double *x, double *up, double *d, int64_t 
     return ST_OK;
 }
 
+namespace {
+
+// Drops the tape; its checkpoint buffers are kept for the next tape, or
+// released with the backward workspace.
+void tape_reset(st_ctx *c, bool keep_buffers)
+{
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &sn : c->snaps) {
+        if (keep_buffers) c->spare.push_back(sn);
+        else (void)hipFree(sn.buf);
+    }
+    c->snaps.clear();
+    if (!keep_buffers) {
+        for (auto &sn : c->spare) (void)hipFree(sn.buf);
+        c->spare.clear();
+        (void)hipFree(c->bwd_ws);
+        c->bwd_ws = nullptr;
+        c->bwd_ws_bytes = 0;
+    }
+    c->tape.clear();
+    c->tape_every = 0;
+}
+
+}  // namespace
+
 st_status st_tape_clear(st_ctx *c)
 {
     if (!c) return ST_ERR_INVALID;
-    (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
-    for (auto &sn : c->snaps) (void)hipFree(sn.buf);
-    c->snaps.clear();
-    c->tape.clear();
-    c->tape_every = 0;
+    tape_reset(c, false);
     return ST_OK;
 }
 
@@ -428,7 +459,8 @@ st_status st_backward(st_ctx *c, const double *dL_dSint, double *dL_du, double *
     if (c->tape.empty()) return fail(c, ST_ERR_STATE, "st_backward: nothing taped");
     ST_HIP(hipSetDevice(c->device));
     ST_HIP(st::launch_backward(c, dL_dSint, dL_du, dL_dd, (hipStream_t)hip_stream));
-    return st_tape_clear(c);
+    tape_reset(c, true);
+    return ST_OK;
 }
 
 st_status st_run_coupled(st_ctx *c, const void *u0, const double *cs, int32_t nsteps, double dt,

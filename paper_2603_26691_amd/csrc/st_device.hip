@@ -510,6 +510,16 @@ struct StepArgs {
     int32_t *flags;
     int32_t deposit;         // 0: move and re-bin only (tape recompute)
     int32_t epoch;           // tag of this step in the device flags
+    // tape recompute: what the reverse of the step reads, saved into a
+    // snapshot buffer at the store's slot indices: the state each slot
+    // starts the step with, its id, and the step's layout (its work items,
+    // and the first slot and slot count of every chunk that has one)
+    T *sv[7];
+    int32_t *sid;
+    int32_t *sitems;
+    int32_t *snitems;
+    int64_t *sbase;
+    int32_t *scnt;
     Params p;
     T dt;
     T dt_h[3];               // dt / h per axis
@@ -643,7 +653,7 @@ static_assert(kSeg <= (1 << kSlotBits) && kMoverStage <= (1 << (32 - 1 - kSlotBi
               "staged mover fields must fit one int32");
 static_assert(kDirBits * 4 <= 32, "direction classes of a group must fit one uint32");
 
-template <class T, class A, int E, int INTERP, int DRAG>
+template <class T, class A, int E, int INTERP, int DRAG, bool SAVE>
 __global__ void __launch_bounds__(kBlock)
      k_step(StepArgs<T, A> a)
 {
@@ -666,12 +676,24 @@ __global__ void __launch_bounds__(kBlock)
     // the grid covers the most items a layout can have, rounded up to whole
     // rounds of the remap
     const int64_t item = xcd_remap(blockIdx.x);
+    if constexpr (SAVE)
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.snitems = *a.nitems;
     if (item >= *a.nitems) return;
     const View<T> &V = a.V;
     const int64_t c = a.items[2 * item];
     const int64_t seg = a.items[2 * item + 1];
     const int64_t base = V.base[c];
     const int32_t cnt = V.cnt[c];
+    if constexpr (SAVE) {
+        if (threadIdx.x == 0) {
+            a.sitems[2 * item] = (int32_t)c;
+            a.sitems[2 * item + 1] = (int32_t)seg;
+            if (seg == 0) {
+                a.sbase[c] = base;
+                a.scnt[c] = cnt;
+            }
+        }
+    }
     const int32_t nd_c = V.ndead[c];   // this step's holes are listed after these
     const int64_t s0 = base + seg * kSeg;
     const int64_t s1 = min(s0 + (int64_t)kSeg, base + (int64_t)cnt);
@@ -755,6 +777,18 @@ __global__ void __launch_bounds__(kBlock)
         if (gi + kBlock < ngroups) load_group(gi + kBlock, Xn, Yn, Zn, UXn, UYn, UZn, DDn);
         const uint32_t o = (uint32_t)gi * G;
         const uint32_t ob = o * (uint32_t)sizeof(T);
+        if constexpr (SAVE) {   // the group as the step finds it, with its ids
+            vst<T, G>(at_byte(a.sv[0] + s0, ob), X);
+            vst<T, G>(at_byte(a.sv[1] + s0, ob), Y);
+            vst<T, G>(at_byte(a.sv[2] + s0, ob), Z);
+            vst<T, G>(at_byte(a.sv[3] + s0, ob), UX);
+            vst<T, G>(at_byte(a.sv[4] + s0, ob), UY);
+            vst<T, G>(at_byte(a.sv[5] + s0, ob), UZ);
+            vst<T, G>(at_byte(a.sv[6] + s0, ob), DD);
+            int32_t I[G];
+            vld<int32_t, G>(at_byte((const int32_t *)V.id + s0, o * 4u), I);
+            vst<int32_t, G>(at_byte(a.sid + s0, o * 4u), I);
+        }
         uint32_t movers = 0, dirs = 0;   // mover bits and 5-bit direction classes
 #pragma unroll
         for (int k = 0; k < G; ++k) {
@@ -1585,11 +1619,17 @@ hipError_t launch_step_t(st_ctx *c, const StepArgs<T, A> &a, hipStream_t s, hipE
 {
     const int64_t round = 8 * kXcdBlock;
     const int64_t grid = (c->max_items + round - 1) / round * round;
+    if constexpr (sizeof(A) == 8) {   // only the forms that tape save
+        if (a.sv[0]) {
+            hipLaunchKernelGGL((k_step<T, A, E, I, D, true>), dim3(grid), dim3(kBlock), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (ev[0])
-        hipExtLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, ev[0],
-                              ev[1], 0, a);
+        hipExtLaunchKernelGGL((k_step<T, A, E, I, D, false>), dim3(grid), dim3(kBlock), 0, s,
+                              ev[0], ev[1], 0, a);
     else
-        hipLaunchKernelGGL((k_step<T, A, E, I, D>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_step<T, A, E, I, D, false>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1712,7 +1752,8 @@ hipError_t launch_init(st_ctx *c, hipStream_t s)
     return launch_items(c, s);
 }
 
-hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStream_t s)
+hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStream_t s,
+                       void *save)
 {
     c->epoch += 1;
     return dispatch(c, [&](auto t, auto acc) -> hipError_t {
@@ -1720,6 +1761,17 @@ hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStre
         using A = decltype(acc);
         StepArgs<T, A> a;
         a.V = view_of<T>(c, 0);
+        for (int k = 0; k < 7; ++k) a.sv[k] = nullptr;
+        if (save) {
+            const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
+            char *b = (char *)save;
+            for (int k = 0; k < 7; ++k) a.sv[k] = (T *)(b + L.state) + k * c->slots;
+            a.sid = (int32_t *)(b + L.id);
+            a.sitems = (int32_t *)(b + L.items);
+            a.snitems = (int32_t *)(b + L.nitems);
+            a.sbase = (int64_t *)(b + L.base);
+            a.scnt = (int32_t *)(b + L.cnt);
+        }
         a.items = c->items;
         a.nitems = c->flags + F_NITEMS;
         a.u = (const T *)u;

@@ -181,6 +181,13 @@ struct st_ctx {
     int tape_every = 0;
     std::vector<st::TapeStep> tape;
     std::vector<st::Snapshot> snaps;  // one per tape_every steps
+    // kept from a consumed tape for the next one (released by st_tape_clear
+    // and st_destroy): checkpoint buffers, and the workspace of st_backward
+    // (the state at the end of the forward run, the saved states of one
+    // segment, the adjoint records and dL/dS by chunk)
+    std::vector<st::Snapshot> spare;
+    void *bwd_ws = nullptr;
+    size_t bwd_ws_bytes = 0;
 
     // coupled run
     void *fieldbuf[2] = {};
@@ -206,7 +213,10 @@ hipError_t launch_items(st_ctx *c, hipStream_t s);
 hipError_t launch_flush_pending(st_ctx *c, hipStream_t s);
 hipError_t launch_zero_sources(st_ctx *c, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
-hipError_t launch_step(st_ctx *c, const void *u, double dt, int record_moves, hipStream_t s);
+// save (a snapshot buffer, or null): the step also writes there what its
+// reverse reads (the state each slot starts with, ids and the layout)
+hipError_t launch_step(st_ctx *c, const void *u, double dt, int deposit, hipStream_t s,
+                       void *save = nullptr);
 hipError_t launch_stage_inject(st_ctx *c, int64_t n, const double *x, const double *up,
                                const double *d, int64_t at, hipStream_t s);
 hipError_t launch_get_particles(st_ctx *c, double *x, double *up, double *d, int64_t *id,
