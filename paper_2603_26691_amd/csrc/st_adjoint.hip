@@ -45,7 +45,6 @@ struct AdjArgs {
     const int32_t *cnt;
     const int32_t *items;
     const int32_t *nitems;
-    int64_t grid;
     const T *u;              // field of the step [3][n2][n1][n0]
     const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
     double *adj;             // adjoint state by id, [P][8]: xbar[3], ubar[3], dbar, unused
@@ -55,7 +54,8 @@ struct AdjArgs {
     double dt;
 };
 
-// One workgroup of 512 threads per work item, two per CU.
+// One workgroup of 256 threads per work item (512 threads at no more than
+// 128 registers, and shorter work items, measured slower).
 constexpr int kAdjBlock = 256;
 
 // Block-wide exclusive scan of one value per thread (kAdjBlock threads);
@@ -82,37 +82,194 @@ __device__ int32_t adj_block_scan(int32_t v, int32_t &total)
 }
 
 // Particles per batch of the trilinear scatter (their stencil offsets and
-// ufbar wait in LDS, in the state precision, ordered by stencil base): about
-// 70 KB of LDS per workgroup in either form, so that two workgroups share a
-// CU.
+// ufbar wait in LDS, in the state precision, ordered by stencil base): two
+// per thread in binary32 (four need more than the 256 registers a thread
+// can hold at two waves per SIMD), one in binary64; 52 KB and 70 KB of LDS.
 template <class T>
-constexpr int adj_batch() { return sizeof(T) == 4 ? 1024 : 256; }
+constexpr int adj_batch() { return sizeof(T) == 4 ? 512 : 256; }
 
-template <class T, int E, int INTERP>
-__global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
+// Field index of cell r of a chunk's tile (its cells E*c - 1 .. E*c + E per
+// axis, wrapped).
+template <int E>
+__device__ __forceinline__ int64_t tile_cell(const Params &p, int cx, int cy, int cz, int r)
+{
+    constexpr int S = E + 2;
+    const int k = r / (S * S), j = (r / S) % S, i = r % S;
+    int gx = cx * E - 1 + i, gy = cy * E - 1 + j, gz = cz * E - 1 + k;
+    gx += gx < 0 ? p.n[0] : 0;
+    gx -= gx >= p.n[0] ? p.n[0] : 0;
+    gy += gy < 0 ? p.n[1] : 0;
+    gy -= gy >= p.n[1] ? p.n[1] : 0;
+    gz += gz < 0 ? p.n[2] : 0;
+    gz -= gz >= p.n[2] ? p.n[2] : 0;
+    return ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx;
+}
+
+// Stages the chunk's tile of the field in LDS, its loads all issued before
+// the first is used.
+template <class T, int E, int NTH>
+__device__ __forceinline__ void stage_tile(const Params &p, const T *u, int cx, int cy, int cz,
+                                           T *tile)
+{
+    constexpr int S3 = (E + 2) * (E + 2) * (E + 2);
+    constexpr int NT = (3 * S3 + NTH - 1) / NTH;
+    const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    T vals[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int t = threadIdx.x + k * NTH;
+        if (t < 3 * S3) {
+            const int comp = t / S3;
+            vals[k] = u[comp * ncell + tile_cell<E>(p, cx, cy, cz, t - comp * S3)];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        const int t = threadIdx.x + k * NTH;
+        if (t < 3 * S3) tile[t] = vals[k];
+    }
+}
+
+// A saved slot holds a particle unless it is past the live ids or a hole (a
+// -1 offset in binary32, a negated diameter in binary64).
+template <class T>
+__device__ __forceinline__ bool adj_live(int64_t id, int64_t count, const T (&st)[7])
+{
+    return id >= 0 && id < count && st[0] >= T(0) && st[6] > T(0);
+}
+
+// Trilinear stencil of a chunk-local position [cells]: lowest corner i0 per
+// axis (-1 .. E-1, a tile index after + 1) and fractional offsets fr.
+template <int E>
+__device__ __forceinline__ void stencil(const double (&xi)[3], int (&i0)[3], double (&fr)[3])
+{
+    for (int ax = 0; ax < 3; ++ax) {
+        const double sx = xi[ax] - 0.5;
+        const double fl = floor(sx);
+        i0[ax] = min(max((int)fl, -1), E - 1);
+        fr[ax] = sx - fl;
+    }
+}
+
+// The reverse of one particle's step.  st: its saved state (chunk-local
+// offsets, velocity, diameter); rc: its adjoint record (xbar[3], ubar[3],
+// dbar), updated in place.  Returns ufbar (the adjoint of the interpolated
+// field velocity, to be scattered onto the tile) and, for trilinear, the
+// stencil (i0, fr); for nearest grid point t0 is the cell's tile index.
+template <class T, int E, bool TRI>
+__device__ __forceinline__ void reverse_particle(const Params &p, double dt, const T *tile,
+                                                 const double *lam, const T (&st)[7],
+                                                 double (&rc)[7], double (&ufb)[3],
+                                                 int (&i0)[3], double (&fr)[3], int &t0)
+{
+    constexpr int S = E + 2;
+    constexpr int S3 = S * S * S;
+    constexpr int E3 = E * E * E;
+    const double xi[3] = {(double)st[0], (double)st[1], (double)st[2]};
+    const double up[3] = {(double)st[3], (double)st[4], (double)st[5]};
+    const double dp = (double)st[6];
+
+    // interpolation at the saved position, in binary64
+    int cl[3];
+    for (int ax = 0; ax < 3; ++ax) cl[ax] = min(max((int)xi[ax], 0), E - 1);
+    double uf[3] = {0.0, 0.0, 0.0};
+    if (TRI) {
+        stencil<E>(xi, i0, fr);
+        t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+            const double w = (bx ? fr[0] : 1.0 - fr[0]) * (by ? fr[1] : 1.0 - fr[1]) *
+                             (bz ? fr[2] : 1.0 - fr[2]);
+            const int tc = t0 + (bz * S + by) * S + bx;
+            for (int comp = 0; comp < 3; ++comp) uf[comp] += w * (double)tile[comp * S3 + tc];
+        }
+    } else {
+        t0 = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
+        for (int comp = 0; comp < 3; ++comp) uf[comp] = (double)tile[comp * S3 + t0];
+    }
+
+    // forward quantities of the step
+    const double tau_s = p.tau_coef * dp * dp;
+    const double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
+    const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
+    const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
+    const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
+    const double tau = p.drag == 1 ? tau_s / f : tau_s;
+    const double mass = p.mass_coef * dp * dp * dp;
+    const double invD = 1.0 / (tau + dt);
+    const double dtD = dt * invD, tauD = tau * invD;
+
+    // reverse
+    const int cell = (cl[2] * E + cl[1]) * E + cl[0];
+    double ub[3];
+    double mbar = 0.0, taubar = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+        const double upn = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) * invD;
+        const double Jbar = -lam[ax * E3 + cell] * p.inv_V;
+        const double wbar = rc[3 + ax] + dt * rc[ax] + mass * Jbar;
+        mbar += Jbar * (upn - up[ax] - p.g[ax] * dt);
+        ufb[ax] = dtD * wbar;
+        taubar += wbar * (up[ax] + dt * p.g[ax] - upn);
+        ub[ax] = -mass * Jbar + tauD * wbar;
+    }
+    taubar *= invD;
+    double Rebar = 0.0;
+    if (Re > 0.0) {
+        Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
+        for (int ax = 0; ax < 3; ++ax) {
+            const double sb = Rebar * Re * slip[ax] / s2;
+            ufb[ax] += sb;
+            ub[ax] -= sb;
+        }
+    }
+    if (TRI) {
+        // the weights' gradients (d/dx of 1 - f is -1/h, of f 1/h) against
+        // the field at each corner
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
+            const int tc = t0 + (bz * S + by) * S + bx;
+            double dot = 0.0;
+            for (int comp = 0; comp < 3; ++comp) dot += (double)tile[comp * S3 + tc] * ufb[comp];
+            const double wx = bx ? fr[0] : 1.0 - fr[0];
+            const double wy = by ? fr[1] : 1.0 - fr[1];
+            const double wz = bz ? fr[2] : 1.0 - fr[2];
+            rc[0] += (bx ? p.inv_h[0] : -p.inv_h[0]) * wy * wz * dot;
+            rc[1] += wx * (by ? p.inv_h[1] : -p.inv_h[1]) * wz * dot;
+            rc[2] += wx * wy * (bz ? p.inv_h[2] : -p.inv_h[2]) * dot;
+        }
+    }
+    for (int ax = 0; ax < 3; ++ax) rc[3 + ax] = ub[ax];
+    rc[6] += (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
+}
+
+// Trilinear: one workgroup per work item, its particles in batches of B.
+// A batch first loads every particle's saved state and id, takes its
+// stencil base and its rank among the batch's particles of that base (an LDS
+// counter), and issues the loads of the adjoint records; the bases' first
+// entries are scanned while the records arrive.  Each particle's reverse
+// then writes its scatter entry (offsets and ufbar, in the state precision)
+// at its place in the batch ordered by base, and every thread sums, in
+// binary64, the entries of the (up to 8) bases whose stencils hold the tile
+// nodes it owns.  Per chunk each node's sum goes to dL/du with one atomic
+// add.
+template <class T, int E>
+__global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
 {
     constexpr int S = E + 2;
     constexpr int S3 = S * S * S;
     constexpr int E3 = E * E * E;
     constexpr int E1 = E + 1;
-    constexpr int NB = E1 * E1 * E1;        // trilinear stencil bases (lowest corners)
+    constexpr int NB = E1 * E1 * E1;         // stencil bases (lowest corners)
     constexpr int B = adj_batch<T>();
-    constexpr bool TRI = INTERP == 0;
+    constexpr int PPT = B / kAdjBlock;       // particles per thread and batch
+    typedef T vec4 __attribute__((ext_vector_type(4)));
     __shared__ T tile[3 * S3];
-    // Nearest grid point: Ubar over the tile, summed in the state precision
-    // with one atomic per particle and component.
-    __shared__ T ubt[TRI ? 1 : 3 * S3];
-    // Trilinear: the reverse of the gather is a scatter to 8 corners.  Instead
-    // of 24 LDS atomics per particle (measured to dominate the kernel), the
-    // particles of a batch are ordered by stencil base and every thread sums
-    // the contributions to the tile nodes it owns, in binary64.
-    __shared__ double nacc[TRI ? 3 * S3 : 1];     // node sums, [3][S3]
-    __shared__ T rf[TRI ? 3 * B : 1];             // fractional offsets f
-    __shared__ T ru[TRI ? 3 * B : 1];             // ufbar
-    __shared__ int32_t rb[TRI ? B : 1];           // base | rank in it << 12, -1 for none
-    __shared__ int32_t perm[TRI ? B : 1];         // batch entries by base
-    __shared__ int32_t bstart[TRI ? NB + 1 : 1];  // first entry of each base
-    __shared__ int32_t bcur[TRI ? NB : 1];        // entries per base
+    __shared__ double nacc[3 * S3];           // node sums, [3][S3]
+    __shared__ vec4 ent[2 * B];               // entries by base: (f, 0), (ufbar, 0)
+    __shared__ int32_t bstart[NB + 1];        // first entry of each base
+    __shared__ int32_t bcur[NB];              // entries per base
 
     const int64_t item = blockIdx.x;
     if (item >= *a.nitems) return;
@@ -124,204 +281,48 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
     const int cy = (int)((c / p.nc[0]) % p.nc[1]);
     const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
     const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
-    const int ox0 = cx * E - 1, oy0 = cy * E - 1, oz0 = cz * E - 1;
 
-    auto tile_cell = [&](int r) -> int64_t {  // field index of tile cell r
-        const int k = r / (S * S), j = (r / S) % S, i = r % S;
-        int gx = ox0 + i, gy = oy0 + j, gz = oz0 + k;
-        gx += gx < 0 ? p.n[0] : 0;
-        gx -= gx >= p.n[0] ? p.n[0] : 0;
-        gy += gy < 0 ? p.n[1] : 0;
-        gy -= gy >= p.n[1] ? p.n[1] : 0;
-        gz += gz < 0 ? p.n[2] : 0;
-        gz -= gz >= p.n[2] ? p.n[2] : 0;
-        return ((int64_t)gz * p.n[1] + gy) * p.n[0] + gx;
-    };
-    // the tile's loads are all issued before the first is used
-    {
-        constexpr int NT = (3 * S3 + kAdjBlock - 1) / kAdjBlock;
-        T vals[NT];
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int t = threadIdx.x + u * kAdjBlock;
-            if (t < 3 * S3) {
-                const int comp = t / S3;
-                vals[u] = a.u[comp * ncell + tile_cell(t - comp * S3)];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int t = threadIdx.x + u * kAdjBlock;
-            if (t < 3 * S3) {
-                tile[t] = vals[u];
-                if (TRI) nacc[t] = 0.0;
-                else ubt[t] = T(0);
-            }
-        }
-    }
-    __syncthreads();
-
-    const double dt = a.dt;
-    const double inv_V = p.inv_V;
+    stage_tile<T, E, kAdjBlock>(p, a.u, cx, cy, cz, tile);
+    for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) nacc[t] = 0.0;
     const double *lam = a.lamC + c * 3 * E3;
-    const int64_t run = TRI ? (int64_t)B : s1 - s0;   // NGP: the whole range at once
-    for (int64_t q0 = s0; q0 < s1; q0 += run) {
-        const int64_t q1 = min(q0 + run, s1);
-        if (TRI) {
-            for (int b = threadIdx.x; b < NB; b += kAdjBlock) bcur[b] = 0;
-            __syncthreads();
-        }
-        // a thread's particles of the batch (PPT of them) load first: ids and
-        // saved states, then the adjoint records the ids address
-        constexpr int PPT = TRI ? 2 : 1;
-        for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += (int64_t)PPT * kAdjBlock) {
-        int64_t idv[PPT];
-        T ls[PPT][7];
-        double lr[PPT][7];
+
+    for (int64_t q0 = s0; q0 < s1; q0 += B) {
+        const int64_t q1 = min(q0 + (int64_t)B, s1);
+        for (int b = threadIdx.x; b < NB; b += kAdjBlock) bcur[b] = 0;
+        __syncthreads();   // also orders the tile and the previous batch's gather
+
+        // load, base and rank; the records' loads fly during the scan
+        int64_t id[PPT];
+        T st[PPT][7];
+        double rc[PPT][7];
+        int32_t slot[PPT];   // base | rank << 12, -1 for none
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            const int64_t q = qb + (int64_t)u * kAdjBlock;
-            idv[u] = -1;
+            const int64_t q = q0 + threadIdx.x + (int64_t)u * kAdjBlock;
+            id[u] = -1;
             if (q < q1) {
-                idv[u] = a.id[q];
-                ls[u][0] = a.ox[q];
-                ls[u][1] = a.oy[q];
-                ls[u][2] = a.oz[q];
-                ls[u][3] = a.vx[q];
-                ls[u][4] = a.vy[q];
-                ls[u][5] = a.vz[q];
-                ls[u][6] = a.d[q];
+                id[u] = a.id[q];
+                st[u][0] = a.ox[q];
+                st[u][1] = a.oy[q];
+                st[u][2] = a.oz[q];
+                st[u][3] = a.vx[q];
+                st[u][4] = a.vy[q];
+                st[u][5] = a.vz[q];
+                st[u][6] = a.d[q];
             }
         }
-#pragma unroll
-        for (int u = 0; u < PPT; ++u)
-            if (idv[u] >= 0 && idv[u] < a.count && ls[u][0] >= T(0) && ls[u][6] > T(0))
-                for (int k = 0; k < 7; ++k) lr[u][k] = a.adj[8 * idv[u] + k];
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            const int64_t q = qb + (int64_t)u * kAdjBlock;
-            if (q >= q1) continue;
-            const int jb = (int)(q - q0);   // entry in the batch
-            const int64_t id = idv[u];
-            // a hole: a -1 offset (binary32) or a negated diameter (binary64)
-            if (id < 0 || id >= a.count || !(ls[u][0] >= T(0) && ls[u][6] > T(0))) {
-                if (TRI) rb[jb] = -1;
-                continue;
-            }
-            const double xi[3] = {(double)ls[u][0], (double)ls[u][1], (double)ls[u][2]};
-            const double up[3] = {(double)ls[u][3], (double)ls[u][4], (double)ls[u][5]};
-            const double dp = (double)ls[u][6];
-
-            // interpolation stencil in binary64 at the saved position
-            int cl[3], i0[3];
-            double om[3][2], dom[3][2];
-            for (int ax = 0; ax < 3; ++ax) {
-                cl[ax] = min(max((int)xi[ax], 0), E - 1);
-                if (TRI) {
-                    const double s = xi[ax] - 0.5;
-                    const double fl = floor(s);
-                    i0[ax] = min(max((int)fl, -1), E - 1);
-                    const double f = s - fl;
-                    om[ax][0] = 1.0 - f;
-                    om[ax][1] = f;
-                    dom[ax][0] = -p.inv_h[ax];
-                    dom[ax][1] = p.inv_h[ax];
-                }
-            }
-            double uf[3] = {0.0, 0.0, 0.0};
-            int tc[8];
-            double w[8];
-            int nk;
-            if (TRI) {
-                nk = 8;
-                const int t0 = ((i0[2] + 1) * S + (i0[1] + 1)) * S + (i0[0] + 1);
-                for (int k = 0; k < 8; ++k) {
-                    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
-                    tc[k] = t0 + (bz * S + by) * S + bx;
-                    w[k] = om[0][bx] * om[1][by] * om[2][bz];
-                }
-            } else {
-                nk = 1;
-                tc[0] = ((cl[2] + 1) * S + (cl[1] + 1)) * S + (cl[0] + 1);
-                w[0] = 1.0;
-            }
-            for (int k = 0; k < nk; ++k)
-                for (int comp = 0; comp < 3; ++comp)
-                    uf[comp] += w[k] * (double)tile[comp * S3 + tc[k]];
-
-            // forward quantities of the step
-            const double tau_s = p.tau_coef * dp * dp;
-            const double slip[3] = {uf[0] - up[0], uf[1] - up[1], uf[2] - up[2]};
-            const double s2 = slip[0] * slip[0] + slip[1] * slip[1] + slip[2] * slip[2];
-            const double Re = p.drag == 1 ? p.re_coef * dp * sqrt(s2) : 0.0;
-            const double f = p.drag == 1 ? 1.0 + 0.15 * pow(Re, 0.687) : 1.0;
-            const double tau = p.drag == 1 ? tau_s / f : tau_s;
-            const double mass = p.mass_coef * dp * dp * dp;
-            const double invD = 1.0 / (tau + dt);
-            const double dtD = dt * invD, tauD = tau * invD;
-            double upn[3];
-            for (int ax = 0; ax < 3; ++ax)
-                upn[ax] = (tau * up[ax] + dt * uf[ax] + tau * dt * p.g[ax]) * invD;
-
-            // reverse
-            const int cell = (cl[2] * E + cl[1]) * E + cl[0];
-            double xb[3], ub[3], ufb[3];
-            double mbar = 0.0, taubar = 0.0;
-            double *rec = a.adj + 8 * id;   // one 64-byte record per particle
-            for (int ax = 0; ax < 3; ++ax) {
-                xb[ax] = lr[u][ax];
-                ub[ax] = lr[u][3 + ax];
-            }
-            for (int ax = 0; ax < 3; ++ax) {
-                const double Jbar = -lam[ax * E3 + cell] * inv_V;
-                const double wbar = ub[ax] + dt * xb[ax] + mass * Jbar;
-                mbar += Jbar * (upn[ax] - up[ax] - p.g[ax] * dt);
-                ufb[ax] = dtD * wbar;
-                taubar += wbar * (up[ax] + dt * p.g[ax] - upn[ax]);
-                ub[ax] = -mass * Jbar + tauD * wbar;
-            }
-            taubar *= invD;
-            double Rebar = 0.0;
-            if (Re > 0.0) {
-                Rebar = -taubar * tau / f * (0.15 * 0.687) * pow(Re, 0.687 - 1.0);
-                for (int ax = 0; ax < 3; ++ax) {
-                    const double sb = Rebar * Re * slip[ax] / s2;
-                    ufb[ax] += sb;
-                    ub[ax] -= sb;
-                }
-            }
-            for (int k = 0; k < nk; ++k) {
-                double dot = 0.0;
-                for (int comp = 0; comp < 3; ++comp) {
-                    if (!TRI) atomicAdd(&ubt[comp * S3 + tc[k]], (T)(w[k] * ufb[comp]));
-                    dot += (double)tile[comp * S3 + tc[k]] * ufb[comp];
-                }
-                if (TRI) {
-                    const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
-                    xb[0] += dom[0][bx] * om[1][by] * om[2][bz] * dot;
-                    xb[1] += om[0][bx] * dom[1][by] * om[2][bz] * dot;
-                    xb[2] += om[0][bx] * om[1][by] * dom[2][bz] * dot;
-                }
-            }
-            if (TRI) {
-                // the scatter waits for the batch: base, offsets and ufbar
-                const int b = ((i0[2] + 1) * E1 + (i0[1] + 1)) * E1 + (i0[0] + 1);
-                for (int ax = 0; ax < 3; ++ax) {
-                    rf[ax * B + jb] = (T)om[ax][1];
-                    ru[ax * B + jb] = (T)ufb[ax];
-                }
-                rb[jb] = b | (atomicAdd(&bcur[b], 1) << 12);
-            }
-            for (int ax = 0; ax < 3; ++ax) {
-                rec[ax] = xb[ax];
-                rec[3 + ax] = ub[ax];
-            }
-            rec[6] = lr[u][6] + (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
+            slot[u] = -1;
+            if (!adj_live(id[u], a.count, st[u])) continue;
+            for (int k = 0; k < 7; ++k) rc[u][k] = a.adj[8 * id[u] + k];
+            const double xi[3] = {(double)st[u][0], (double)st[u][1], (double)st[u][2]};
+            int i0[3];
+            double fr[3];
+            stencil<E>(xi, i0, fr);
+            const int b = ((i0[2] + 1) * E1 + (i0[1] + 1)) * E1 + (i0[0] + 1);
+            slot[u] = b | (atomicAdd(&bcur[b], 1) << 12);
         }
-        }
-        if (!TRI) break;
-
-        // order the batch by stencil base (a counting sort in LDS) ...
         __syncthreads();
         {
             constexpr int PER = (NB + kAdjBlock - 1) / kAdjBlock;
@@ -344,14 +345,25 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             if (threadIdx.x == 0) bstart[NB] = total;
         }
         __syncthreads();
-        for (int jb = threadIdx.x; jb < (int)(q1 - q0); jb += kAdjBlock) {
-            const int32_t w = rb[jb];
-            if (w >= 0) perm[bstart[w & 4095] + (w >> 12)] = jb;
+
+        // the reverse of each particle; its entry goes to its place by base
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            if (slot[u] < 0) continue;
+            double ufb[3], fr[3];
+            int i0[3], t0;
+            reverse_particle<T, E, true>(p, a.dt, tile, lam, st[u], rc[u], ufb, i0, fr, t0);
+            const int e = bstart[slot[u] & 4095] + (slot[u] >> 12);
+            ent[2 * e] = vec4{(T)fr[0], (T)fr[1], (T)fr[2], T(0)};
+            ent[2 * e + 1] = vec4{(T)ufb[0], (T)ufb[1], (T)ufb[2], T(0)};
+            double *rec = a.adj + 8 * id[u];
+            for (int k = 0; k < 7; ++k) rec[k] = rc[u][k];
         }
         __syncthreads();
-        // ... and let every node gather from the (up to 8) bases whose stencil
-        // holds it: node = base + (bx, by, bz), weight prod over the axes of
-        // f (offset 1) or 1 - f (offset 0)
+
+        // every node gathers from the bases whose stencil holds it: node =
+        // base + (bx, by, bz), weight the product over the axes of f
+        // (offset 1) or 1 - f (offset 0)
         for (int n = threadIdx.x; n < S3; n += kAdjBlock) {   // nodes owned by this thread
             const int nx = n % S, ny = (n / S) % S, nz = n / (S * S);
             // per row (by, bz) of bases the node's x-neighbours nx - 1 (offset
@@ -373,37 +385,74 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_step(AdjArgs<T> a)
             for (int k = 0; k < 4; ++k) {
                 const int by = k & 1, bz = k >> 1;
                 for (int e = lo[k]; e < hi[k]; ++e) {
-                    const int jb = perm[e];
-                    const double fx = (double)rf[jb], fy = (double)rf[B + jb],
-                                 fz = (double)rf[2 * B + jb];
+                    const vec4 fv = ent[2 * e], uv = ent[2 * e + 1];
+                    const double fx = (double)fv.x, fy = (double)fv.y, fz = (double)fv.z;
                     const double wk = (e < mid[k] ? fx : 1.0 - fx) * (by ? fy : 1.0 - fy) *
                                       (bz ? fz : 1.0 - fz);
-                    sum[0] += wk * (double)ru[jb];
-                    sum[1] += wk * (double)ru[B + jb];
-                    sum[2] += wk * (double)ru[2 * B + jb];
+                    sum[0] += wk * (double)uv.x;
+                    sum[1] += wk * (double)uv.y;
+                    sum[2] += wk * (double)uv.z;
                 }
             }
             for (int comp = 0; comp < 3; ++comp) nacc[comp * S3 + n] += sum[comp];
         }
-        __syncthreads();   // the next batch overwrites the entries
     }
-    if (TRI) {
-        // each node's sum was last written by this thread
-        for (int n = threadIdx.x; n < S3; n += kAdjBlock) {
-            const int64_t g = tile_cell(n);
-            for (int comp = 0; comp < 3; ++comp) {
-                const double v = nacc[comp * S3 + n];
-                if (v != 0.0) atomicAdd(a.Ubar + comp * ncell + g, v);
-            }
+    __syncthreads();
+    for (int n = threadIdx.x; n < S3; n += kAdjBlock) {
+        const int64_t g = tile_cell<E>(p, cx, cy, cz, n);
+        for (int comp = 0; comp < 3; ++comp) {
+            const double v = nacc[comp * S3 + n];
+            if (v != 0.0) atomicAdd(a.Ubar + comp * ncell + g, v);
         }
-        return;
+    }
+}
+
+// Nearest grid point: the reverse of each particle adds its ufbar to its
+// cell of the tile with one LDS atomic per component, in the state
+// precision; per chunk each tile cell's sum goes to dL/du with one atomic.
+template <class T, int E>
+__global__ void __launch_bounds__(kAdjBlock) k_adjoint_ngp(AdjArgs<T> a)
+{
+    constexpr int S = E + 2;
+    constexpr int S3 = S * S * S;
+    constexpr int E3 = E * E * E;
+    __shared__ T tile[3 * S3];
+    __shared__ T ubt[3 * S3];
+
+    const int64_t item = blockIdx.x;
+    if (item >= *a.nitems) return;
+    const Params &p = a.p;
+    const int64_t c = a.items[2 * item], seg = a.items[2 * item + 1];
+    const int64_t s0 = a.base[c] + seg * kSeg;
+    const int64_t s1 = min(s0 + (int64_t)kSeg, a.base[c] + (int64_t)a.cnt[c]);
+    const int cx = (int)(c % p.nc[0]);
+    const int cy = (int)((c / p.nc[0]) % p.nc[1]);
+    const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
+    const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
+
+    stage_tile<T, E, kAdjBlock>(p, a.u, cx, cy, cz, tile);
+    for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) ubt[t] = T(0);
+    __syncthreads();
+    const double *lam = a.lamC + c * 3 * E3;
+    for (int64_t q = s0 + threadIdx.x; q < s1; q += kAdjBlock) {
+        const int64_t id = a.id[q];
+        const T st[7] = {a.ox[q], a.oy[q], a.oz[q], a.vx[q], a.vy[q], a.vz[q], a.d[q]};
+        if (!adj_live(id, a.count, st)) continue;
+        double rc[7];
+        for (int k = 0; k < 7; ++k) rc[k] = a.adj[8 * id + k];
+        double ufb[3], fr[3];
+        int i0[3], t0;
+        reverse_particle<T, E, false>(p, a.dt, tile, lam, st, rc, ufb, i0, fr, t0);
+        for (int comp = 0; comp < 3; ++comp) atomicAdd(&ubt[comp * S3 + t0], (T)ufb[comp]);
+        double *rec = a.adj + 8 * id;
+        for (int k = 0; k < 7; ++k) rec[k] = rc[k];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) {
         const double v = (double)ubt[t];
         if (v != 0.0) {
             const int comp = t / S3;
-            atomicAdd(a.Ubar + comp * ncell + tile_cell(t - comp * S3), v);
+            atomicAdd(a.Ubar + comp * ncell + tile_cell<E>(p, cx, cy, cz, t - comp * S3), v);
         }
     }
 }
@@ -465,7 +514,6 @@ AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const doubl
     a.cnt = reinterpret_cast<const int32_t *>(snap + L.cnt);
     a.items = reinterpret_cast<const int32_t *>(snap + L.items);
     a.nitems = reinterpret_cast<const int32_t *>(snap + L.nitems);
-    a.grid = c->max_items;
     a.u = reinterpret_cast<const T *>(ts.u);
     a.lamC = lamC;
     a.adj = adj;
@@ -483,16 +531,16 @@ hipError_t launch_adjoint_step(st_ctx *c, const AdjArgs<T> &a, hipStream_t s)
     const bool ngp = c->prm.interp == 1;
     switch (c->prm.E) {
     case 2:
-        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 2, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint_step<T, 2, 0>), g, b, 0, s, a);
+        if (ngp) hipLaunchKernelGGL((k_adjoint_ngp<T, 2>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_tri<T, 2>), g, b, 0, s, a);
         break;
     case 4:
-        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 4, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint_step<T, 4, 0>), g, b, 0, s, a);
+        if (ngp) hipLaunchKernelGGL((k_adjoint_ngp<T, 4>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_tri<T, 4>), g, b, 0, s, a);
         break;
     default:
-        if (ngp) hipLaunchKernelGGL((k_adjoint_step<T, 8, 1>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_adjoint_step<T, 8, 0>), g, b, 0, s, a);
+        if (ngp) hipLaunchKernelGGL((k_adjoint_ngp<T, 8>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_adjoint_tri<T, 8>), g, b, 0, s, a);
         break;
     }
     return hipGetLastError();
