@@ -224,21 +224,24 @@ __device__ __forceinline__ void reverse_particle(const Params &p, double dt, con
         }
     }
     if (TRI) {
-        // the weights' gradients (d/dx of 1 - f is -1/h, of f 1/h) against
-        // the field at each corner
+        // the position adjoint: the weights' gradients (d/dx of 1 - f is
+        // -1/h, of f 1/h) against dot_k = U_k . ufbar at each corner k, which
+        // per axis is 1/h times the bilinear interpolation, over the other
+        // two axes, of the corner differences along it
+        double dot[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int bx = k & 1, by = (k >> 1) & 1, bz = (k >> 2) & 1;
-            const int tc = t0 + (bz * S + by) * S + bx;
-            double dot = 0.0;
-            for (int comp = 0; comp < 3; ++comp) dot += (double)tile[comp * S3 + tc] * ufb[comp];
-            const double wx = bx ? fr[0] : 1.0 - fr[0];
-            const double wy = by ? fr[1] : 1.0 - fr[1];
-            const double wz = bz ? fr[2] : 1.0 - fr[2];
-            rc[0] += (bx ? p.inv_h[0] : -p.inv_h[0]) * wy * wz * dot;
-            rc[1] += wx * (by ? p.inv_h[1] : -p.inv_h[1]) * wz * dot;
-            rc[2] += wx * wy * (bz ? p.inv_h[2] : -p.inv_h[2]) * dot;
+            const int tc = t0 + (((k >> 2) & 1) * S + ((k >> 1) & 1)) * S + (k & 1);
+            dot[k] = 0.0;
+            for (int comp = 0; comp < 3; ++comp) dot[k] += (double)tile[comp * S3 + tc] * ufb[comp];
         }
+        auto lerp = [](double a, double b, double t) { return a + t * (b - a); };
+        rc[0] += p.inv_h[0] * lerp(lerp(dot[1] - dot[0], dot[3] - dot[2], fr[1]),
+                                   lerp(dot[5] - dot[4], dot[7] - dot[6], fr[1]), fr[2]);
+        rc[1] += p.inv_h[1] * lerp(lerp(dot[2] - dot[0], dot[3] - dot[1], fr[0]),
+                                   lerp(dot[6] - dot[4], dot[7] - dot[5], fr[0]), fr[2]);
+        rc[2] += p.inv_h[2] * lerp(lerp(dot[4] - dot[0], dot[5] - dot[1], fr[0]),
+                                   lerp(dot[6] - dot[2], dot[7] - dot[3], fr[0]), fr[1]);
     }
     for (int ax = 0; ax < 3; ++ax) rc[3 + ax] = ub[ax];
     rc[6] += (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
