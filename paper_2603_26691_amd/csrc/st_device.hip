@@ -881,7 +881,11 @@ __global__ void __launch_bounds__(kBlock)
                 for (int ax = 0; ax < 3; ++ax) {
                     T v = xg[ax] + upn[ax] * dt;
                     if (v >= p.Lf[ax]) v -= p.Lf[ax];
-                    if (v < T(0)) v += p.Lf[ax];
+                    else if (v < T(0)) v += p.Lf[ax];
+                    if (!(v >= T(0) && v < p.Lf[ax])) {   // moved more than a domain length
+                        v = fmodf(v, p.Lf[ax]);
+                        if (v < T(0)) v += p.Lf[ax];
+                    }
                     if (v >= p.Lf[ax]) v = T(0);
                     xn[ax] = v;
                     const int cc = ax == 0 ? cx : ax == 1 ? cy : cz;

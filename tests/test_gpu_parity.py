@@ -39,7 +39,7 @@ def _run_lockstep(orc, w, form, nsteps=4, interp=0, nsub=1, dt=None, drag="stoke
     t.inject(x, up, d)
     Udev, Uor = fields(w, form)
     out = lockstep_check(t, orc, oracle_mesh(w, interp, drag), Udev, Uor, dt or w.dt, nsteps,
-                         TOL[form], nsub=nsub, band_=band(form, w.n))
+                         TOL[form], nsub=nsub, band_=band(form, w.n), ngp=bool(interp))
     print(form, w.name, out)
     t.close()
     return out
@@ -67,19 +67,19 @@ def test_lockstep_schiller_naumann_ngp_substeps(orc, form):
     _run_lockstep(orc, w, form, nsteps=2, interp=1, nsub=3, dt=3e-4, drag="schiller_naumann")
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+@pytest.mark.parametrize("form", FORMS)
 def test_lockstep_ngp(orc, form):
     w = workload("tg32", P=20000, noise=0.1)
     _run_lockstep(orc, w, form, nsteps=3, interp=1)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+@pytest.mark.parametrize("form", FORMS)
 def test_lockstep_substeps(orc, form):
     w = workload("tg32", P=10000, noise=0.1)
     _run_lockstep(orc, w, form, nsteps=2, nsub=3, dt=3e-4)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+@pytest.mark.parametrize("form", FORMS)
 def test_lockstep_chunk_split_over_items(orc, form):
     # 16^3 mesh = 8 chunks with 25000 droplets each: every chunk is split
     # over two work items and deposits with atomics
@@ -87,7 +87,7 @@ def test_lockstep_chunk_split_over_items(orc, form):
     _run_lockstep(orc, w, form, nsteps=3)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+@pytest.mark.parametrize("form", FORMS)
 def test_lockstep_many_movers(orc, form):
     # 16^3 mesh = 8 chunks of ~19000 droplets and a step of about 0.8 cells:
     # thousands of chunk crossers per chunk and step (the workgroup-wide fill)
@@ -98,11 +98,11 @@ def test_lockstep_many_movers(orc, form):
 @pytest.mark.parametrize("edge", [2, 4])
 def test_lockstep_small_chunks(orc, edge):
     w = workload("tg32", n=(8, 8, 16), L=(0.05, 0.05, 0.1), P=5000, noise=0.2, chunk_edge=edge)
-    _run_lockstep(orc, w, "fp64", nsteps=3)
-    _run_lockstep(orc, w, "fp32_local", nsteps=3)
+    for form in FORMS:
+        _run_lockstep(orc, w, form, nsteps=3)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+@pytest.mark.parametrize("form", FORMS)
 def test_lockstep_non_cubic(orc, form):
     w = workload("tg32", n=(32, 16, 8), L=(0.1, 0.04, 0.025), P=20000, noise=0.1,
                  g=(1.0, -2.0, -9.81))
