@@ -50,7 +50,7 @@
 namespace st {
 namespace {
 
-constexpr int kScan1Max = 1 << 16;  // largest scan done by one workgroup
+constexpr int kScan1Max = 1 << 13;  // largest scan done by one workgroup
 constexpr int kScanBlock = 1024;    // elements per block of the multi-block scan
 
 enum Gate { G_ALWAYS = 0, G_FULL = 1, G_MOVERS = 2 };
@@ -384,15 +384,21 @@ struct ItemArgs {
     int32_t dead_limit;  // more holes than this force a full re-bin at the next step
 };
 
-__device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
+// chunk c's work items [o, e) (its offsets in the item list), and the reset
+// of its counters
+__device__ __forceinline__ void write_items_at(const ItemArgs &a, int64_t c, int32_t o, int32_t e)
 {
-    const int32_t o = a.noff[c], e = a.noff[c + 1];
     for (int32_t s = 0; s < e - o; ++s) {
         a.items[2 * (int64_t)(o + s)] = (int32_t)c;
         a.items[2 * (int64_t)(o + s) + 1] = s;
     }
     a.out_cnt[c] = 0;
     a.in_cnt[c] = 0;
+}
+
+__device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
+{
+    write_items_at(a, c, a.noff[c], a.noff[c + 1]);
 }
 
 __device__ __forceinline__ void finish_flags(const ItemArgs &a)
@@ -427,19 +433,25 @@ __global__ void k_items(ItemArgs a)
 // holes no arrival took stay listed (and marked: a -1 offset or a negated
 // diameter).  Returns the chunk's holes.
 template <class T>
-__device__ __forceinline__ int32_t count_chunk(const View<T> &V, const int32_t *out_cnt,
-                                               const int32_t *in_cnt, int64_t c)
+__device__ __forceinline__ int32_t count_chunk_from(const View<T> &V, int32_t out, int32_t in,
+                                                    int32_t nd, int32_t cnt, int64_t c)
 {
-    const int32_t out = out_cnt[c], in = in_cnt[c], nd = V.ndead[c];
     const int32_t h = nd + out;
     if (out == 0 && in == 0) return nd;
     if (in >= h) {
-        V.cnt[c] += in - h;
+        V.cnt[c] = cnt + in - h;
         V.ndead[c] = 0;
         return 0;
     }
     V.ndead[c] = h - in;
     return h - in;
+}
+
+template <class T>
+__device__ __forceinline__ int32_t count_chunk(const View<T> &V, const int32_t *out_cnt,
+                                               const int32_t *in_cnt, int64_t c)
+{
+    return count_chunk_from(V, out_cnt[c], in_cnt[c], V.ndead[c], V.cnt[c], c);
 }
 
 // one workgroup, after the arrivals or the re-keyed count (C <= kScan1Max).
@@ -460,15 +472,47 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
         block_scan_all<int32_t>(rekeyed, a.C, a.noff);
         return;
     }
+    // a thread's chunks (at most kScan1Max / 1024): every load is issued
+    // before the first store, so that the latencies overlap
+    constexpr int PT = kScan1Max / 1024;
+    int32_t out[PT], in[PT], nd[PT], cn[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t c = k * 1024 + threadIdx.x;
+        out[k] = in[k] = nd[k] = cn[k] = 0;
+        if (c < a.C) {
+            out[k] = a.out_cnt[c];
+            in[k] = a.in_cnt[c];
+            nd[k] = V.ndead[c];
+            cn[k] = V.cnt[c];
+        }
+    }
     int32_t dead = 0;
-    for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x)
-        dead += count_chunk(V, a.out_cnt, a.in_cnt, c);
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t c = k * 1024 + threadIdx.x;
+        if (c < a.C) dead += count_chunk_from(V, out[k], in[k], nd[k], cn[k], c);
+    }
     int32_t total;
     block_excl_scan<int32_t>(dead, total);   // ends with a barrier: the counts are visible
     if (threadIdx.x == 0) a.flags[F_DEAD] = total;
     block_scan_all<int32_t>(now, a.C, a.noff);
     __syncthreads();
-    for (int64_t c = threadIdx.x; c < a.C; c += blockDim.x) write_items(a, c);
+    int32_t o[PT], e[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t c = k * 1024 + threadIdx.x;
+        o[k] = e[k] = 0;
+        if (c < a.C) {
+            o[k] = a.noff[c];
+            e[k] = a.noff[c + 1];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int64_t c = k * 1024 + threadIdx.x;
+        if (c < a.C) write_items_at(a, c, o[k], e[k]);
+    }
     if (threadIdx.x == 0) finish_flags(a);
 }
 
