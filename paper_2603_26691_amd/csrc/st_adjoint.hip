@@ -388,13 +388,14 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
             for (int k = 0; k < 4; ++k) {
                 const int by = k & 1, bz = k >> 1;
                 for (int e = lo[k]; e < hi[k]; ++e) {
+                    // each term in the state precision (as its offsets and
+                    // ufbar are), the sum in binary64
                     const vec4 fv = ent[2 * e], uv = ent[2 * e + 1];
-                    const double fx = (double)fv.x, fy = (double)fv.y, fz = (double)fv.z;
-                    const double wk = (e < mid[k] ? fx : 1.0 - fx) * (by ? fy : 1.0 - fy) *
-                                      (bz ? fz : 1.0 - fz);
-                    sum[0] += wk * (double)uv.x;
-                    sum[1] += wk * (double)uv.y;
-                    sum[2] += wk * (double)uv.z;
+                    const T wk = (e < mid[k] ? fv.x : T(1) - fv.x) * (by ? fv.y : T(1) - fv.y) *
+                                 (bz ? fv.z : T(1) - fv.z);
+                    sum[0] += (double)(wk * uv.x);
+                    sum[1] += (double)(wk * uv.y);
+                    sum[2] += (double)(wk * uv.z);
                 }
             }
             for (int comp = 0; comp < 3; ++comp) nacc[comp * S3 + n] += sum[comp];
