@@ -257,6 +257,50 @@ def test_checkpoint_interval_does_not_change_gradient():
         assert _rel(g[0], grads[0][0]) < 1e-12 and _rel(g[1], grads[0][1]) < 1e-12
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_repeated_taped_runs_reuse_buffers(form):
+    """st_backward keeps the checkpoint buffers and its workspace for the next
+    taped run: a second and a third taped run on the same tracker (other
+    checkpoint intervals, so the workspace grows and is reused) give the
+    gradients of a fresh tracker started from the same state, and
+    st_tape_clear releases everything without disturbing the next run."""
+    import torch
+    w = _case(P=3000, nsteps=8)
+    x, up, d = w.particles()
+    Udev, _ = fields(w, form)
+    a = tracker(w, form)
+    a.inject(x, up, d)
+    b = tracker(w, form)
+    b.inject(x, up, d)
+    lam = None
+    for cycle, K in enumerate((4, 8, 3)):
+        for _ in range(w.nsteps):
+            a.step(Udev, w.dt, tape=K)
+        Sa = a.sources(reset=True)
+        if lam is None:
+            lam = torch.sin(Sa * 1e3).contiguous()
+        ga = [g.cpu().numpy() for g in a.backward(lam)]
+        # the fresh reference: the same start state (b untaped to here), then
+        # the same taped run in a tracker that never kept a tape
+        c = tracker(w, form)
+        sb = state(b)
+        order = np.argsort(sb["id"])
+        c.inject(sb["x"][order], sb["up"][order], sb["d"][order])
+        for _ in range(w.nsteps):
+            c.step(Udev, w.dt, tape=K)
+            b.step(Udev, w.dt)
+        c.sources(reset=True)
+        b.sources(reset=True)
+        gc = [g.cpu().numpy() for g in c.backward(lam)]
+        c.close()
+        tol = 1e-12 if form == "fp64" else 1e-6
+        assert _rel(ga[0], gc[0]) < tol and _rel(ga[1], gc[1]) < tol, (cycle, K)
+        if cycle == 1:
+            a.tape_clear()   # nothing taped: releases the kept buffers
+    a.close()
+    b.close()
+
+
 def test_adjoint_against_finite_differences():
     """Central differences of the GPU's own FP64 forward (h = 1e-3 relative
     for diameters, 1e-3 m/s for field entries) on 32 sampled entries."""
