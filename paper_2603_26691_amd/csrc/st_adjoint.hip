@@ -84,7 +84,7 @@ __device__ int32_t adj_block_scan(int32_t v, int32_t &total)
 // Particles per batch of the trilinear scatter (their stencil offsets and
 // ufbar wait in LDS, in the state precision, ordered by stencil base): two
 // per thread in binary32 (four need more than the 256 registers a thread
-// can hold at two waves per SIMD), one in binary64; 52 KB and 70 KB of LDS.
+// can hold at two waves per SIMD), one in binary64; 58 KB and 70 KB of LDS.
 template <class T>
 constexpr int adj_batch() { return sizeof(T) == 4 ? 512 : 256; }
 
