@@ -24,8 +24,13 @@
 // each segment is recomputed from its checkpoint (deposit off), each step
 // saving the state it starts from, the ids and its layout as it streams
 // them, and then reversed newest first.
-// The per-particle adjoint state is kept by particle id, so the re-binning
-// between steps needs no special treatment.
+// The per-particle adjoint state is kept in one 64-byte record per particle,
+// indexed within a segment by the particle's slot in the segment's
+// checkpoint (its anchor): the restored checkpoint's ids are replaced by the
+// slot indices before the recomputation, so every saved step carries anchors
+// instead of ids, and since particles that stay in their chunk keep their
+// slots, each step reads and writes the records nearly in slot order.
+// Between segments the records pass through an array by particle id.
 #include "st_internal.h"
 
 #include <math.h>
@@ -47,46 +52,19 @@ struct AdjArgs {
     const int32_t *nitems;
     const T *u;              // field of the step [3][n2][n1][n0]
     const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
-    double *adj;             // adjoint state by id, [P][8]: xbar[3], ubar[3], dbar, unused
+    double *adj;             // adjoint records by anchor, [nrec][8]: xbar[3], ubar[3], dbar, unused
     double *Ubar;            // dL/du [3][n2][n1][n0]
-    int64_t count;
+    int64_t nrec;            // records (the store's slots)
     Params p;
     double dt;
 };
 
-// One workgroup of 256 threads per work item (512 threads at no more than
-// 128 registers, and shorter work items, measured slower).
+// One workgroup of 256 threads per work item, two particles per thread and
+// pass (one per pass, 384-thread groups at three waves per SIMD, three or
+// four per pass, and the next pass's loads issued during the current one
+// measured no faster).
 constexpr int kAdjBlock = 256;
-
-// Block-wide exclusive scan of one value per thread (kAdjBlock threads);
-// returns the prefix and the block total.
-__device__ int32_t adj_block_scan(int32_t v, int32_t &total)
-{
-    __shared__ int32_t ws[kAdjBlock / 64];
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    int32_t incl = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
-    }
-    if (lane == 63) ws[wave] = incl;
-    __syncthreads();
-    int32_t before = 0;
-    total = 0;
-    for (int k = 0; k < kAdjBlock / 64; ++k) {
-        if (k < wave) before += ws[k];
-        total += ws[k];
-    }
-    __syncthreads();
-    return before + incl - v;
-}
-
-// Particles per batch of the trilinear scatter (their stencil offsets and
-// ufbar wait in LDS, in the state precision, ordered by stencil base): two
-// per thread in binary32 (four need more than the 256 registers a thread
-// can hold at two waves per SIMD), one in binary64; 58 KB and 70 KB of LDS.
-template <class T>
-constexpr int adj_batch() { return sizeof(T) == 4 ? 512 : 256; }
+constexpr int kAdjPPT = 2;
 
 // Field index of cell r of a chunk's tile (its cells E*c - 1 .. E*c + E per
 // axis, wrapped).
@@ -130,12 +108,13 @@ __device__ __forceinline__ void stage_tile(const Params &p, const T *u, int cx, 
     }
 }
 
-// A saved slot holds a particle unless it is past the live ids or a hole (a
-// -1 offset in binary32, a negated diameter in binary64).
+// A saved slot holds a particle unless its anchor is -1 (no particle at
+// that slot of the checkpoint) or it is a hole (a -1 offset in binary32, a
+// negated diameter in binary64).
 template <class T>
-__device__ __forceinline__ bool adj_live(int64_t id, int64_t count, const T (&st)[7])
+__device__ __forceinline__ bool adj_live(int64_t anchor, int64_t nrec, const T (&st)[7])
 {
-    return id >= 0 && id < count && st[0] >= T(0) && st[6] > T(0);
+    return anchor >= 0 && anchor < nrec && st[0] >= T(0) && st[6] > T(0);
 }
 
 // Trilinear stencil of a chunk-local position [cells]: lowest corner i0 per
@@ -247,32 +226,22 @@ __device__ __forceinline__ void reverse_particle(const Params &p, double dt, con
     rc[6] += (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
 }
 
-// Trilinear: one workgroup per work item, its particles in batches of B.
-// A batch first loads every particle's saved state and id, takes its
-// stencil base and its rank among the batch's particles of that base (an LDS
-// counter), and issues the loads of the adjoint records; the bases' first
-// entries are scanned while the records arrive.  Each particle's reverse
-// then writes its scatter entry (offsets and ufbar, in the state precision)
-// at its place in the batch ordered by base, and every thread sums, in
-// binary64, the entries of the (up to 8) bases whose stencils hold the tile
-// nodes it owns.  Per chunk each node's sum goes to dL/du with one atomic
-// add.
+// Trilinear: one workgroup per work item.  Each thread reverses kAdjPPT
+// particles per pass, their loads issued together (saved states and anchors
+// first, then the records the anchors address), and adds each particle's
+// eight weighted ufbar terms to the tile's node sums in LDS: each term formed
+// in the state precision from the particle's stencil offsets and ufbar
+// rounded to it, the sums kept in binary64 (LDS atomic adds).  Per chunk each
+// node's sum goes to dL/du with one atomic add.
 template <class T, int E>
 __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
 {
     constexpr int S = E + 2;
     constexpr int S3 = S * S * S;
     constexpr int E3 = E * E * E;
-    constexpr int E1 = E + 1;
-    constexpr int NB = E1 * E1 * E1;         // stencil bases (lowest corners)
-    constexpr int B = adj_batch<T>();
-    constexpr int PPT = B / kAdjBlock;       // particles per thread and batch
-    typedef T vec4 __attribute__((ext_vector_type(4)));
+    constexpr int PPT = kAdjPPT;
     __shared__ T tile[3 * S3];
     __shared__ double nacc[3 * S3];           // node sums, [3][S3]
-    __shared__ vec4 ent[2 * B];               // entries by base: (f, 0), (ufbar, 0)
-    __shared__ int32_t bstart[NB + 1];        // first entry of each base
-    __shared__ int32_t bcur[NB];              // entries per base
 
     const int64_t item = blockIdx.x;
     if (item >= *a.nitems) return;
@@ -287,24 +256,19 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
 
     stage_tile<T, E, kAdjBlock>(p, a.u, cx, cy, cz, tile);
     for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) nacc[t] = 0.0;
+    __syncthreads();
     const double *lam = a.lamC + c * 3 * E3;
 
-    for (int64_t q0 = s0; q0 < s1; q0 += B) {
-        const int64_t q1 = min(q0 + (int64_t)B, s1);
-        for (int b = threadIdx.x; b < NB; b += kAdjBlock) bcur[b] = 0;
-        __syncthreads();   // also orders the tile and the previous batch's gather
-
-        // load, base and rank; the records' loads fly during the scan
-        int64_t id[PPT];
+    for (int64_t q0 = s0; q0 < s1; q0 += PPT * kAdjBlock) {
+        int64_t an[PPT];
         T st[PPT][7];
         double rc[PPT][7];
-        int32_t slot[PPT];   // base | rank << 12, -1 for none
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             const int64_t q = q0 + threadIdx.x + (int64_t)u * kAdjBlock;
-            id[u] = -1;
-            if (q < q1) {
-                id[u] = a.id[q];
+            an[u] = -1;
+            if (q < s1) {
+                an[u] = a.id[q];
                 st[u][0] = a.ox[q];
                 st[u][1] = a.oy[q];
                 st[u][2] = a.oz[q];
@@ -314,91 +278,33 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
                 st[u][6] = a.d[q];
             }
         }
+        bool live[PPT];
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            slot[u] = -1;
-            if (!adj_live(id[u], a.count, st[u])) continue;
-            for (int k = 0; k < 7; ++k) rc[u][k] = a.adj[8 * id[u] + k];
-            const double xi[3] = {(double)st[u][0], (double)st[u][1], (double)st[u][2]};
-            int i0[3];
-            double fr[3];
-            stencil<E>(xi, i0, fr);
-            const int b = ((i0[2] + 1) * E1 + (i0[1] + 1)) * E1 + (i0[0] + 1);
-            slot[u] = b | (atomicAdd(&bcur[b], 1) << 12);
+            live[u] = adj_live(an[u], a.nrec, st[u]);
+            if (live[u])
+                for (int k = 0; k < 7; ++k) rc[u][k] = a.adj[8 * an[u] + k];
         }
-        __syncthreads();
-        {
-            constexpr int PER = (NB + kAdjBlock - 1) / kAdjBlock;
-            int32_t v[PER];
-            int32_t sum = 0;
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int b = threadIdx.x * PER + k;
-                v[k] = b < NB ? bcur[b] : 0;
-                sum += v[k];
-            }
-            int32_t total;
-            int32_t ex = adj_block_scan(sum, total);
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int b = threadIdx.x * PER + k;
-                if (b < NB) bstart[b] = ex;
-                ex += v[k];
-            }
-            if (threadIdx.x == 0) bstart[NB] = total;
-        }
-        __syncthreads();
-
-        // the reverse of each particle; its entry goes to its place by base
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            if (slot[u] < 0) continue;
+            if (!live[u]) continue;
             double ufb[3], fr[3];
             int i0[3], t0;
             reverse_particle<T, E, true>(p, a.dt, tile, lam, st[u], rc[u], ufb, i0, fr, t0);
-            const int e = bstart[slot[u] & 4095] + (slot[u] >> 12);
-            ent[2 * e] = vec4{(T)fr[0], (T)fr[1], (T)fr[2], T(0)};
-            ent[2 * e + 1] = vec4{(T)ufb[0], (T)ufb[1], (T)ufb[2], T(0)};
-            double *rec = a.adj + 8 * id[u];
+            double *rec = a.adj + 8 * an[u];
             for (int k = 0; k < 7; ++k) rec[k] = rc[u][k];
-        }
-        __syncthreads();
-
-        // every node gathers from the bases whose stencil holds it: node =
-        // base + (bx, by, bz), weight the product over the axes of f
-        // (offset 1) or 1 - f (offset 0)
-        for (int n = threadIdx.x; n < S3; n += kAdjBlock) {   // nodes owned by this thread
-            const int nx = n % S, ny = (n / S) % S, nz = n / (S * S);
-            // per row (by, bz) of bases the node's x-neighbours nx - 1 (offset
-            // 1) and nx (offset 0) are adjacent bases, so their entries are
-            // one range [lo, hi), split at mid; all 12 bounds load first
-            const int xa = max(nx - 1, 0), xl = min(nx, E);
-            int lo[4], mid[4], hi[4];
+            const T f[3] = {(T)fr[0], (T)fr[1], (T)fr[2]};
+            const T ub[3] = {(T)ufb[0], (T)ufb[1], (T)ufb[2]};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int y = ny - (k & 1), z = nz - (k >> 1);
-                const bool ok = y >= 0 && z >= 0 && y <= E && z <= E;
-                const int row = (z * E1 + y) * E1;
-                lo[k] = ok ? bstart[row + xa] : 0;
-                hi[k] = ok ? bstart[row + xl + 1] : 0;
-                mid[k] = !ok ? 0 : nx == 0 ? lo[k] : nx > E ? hi[k] : bstart[row + nx];
-            }
-            double sum[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 8; ++k) {
+                const int bx = k & 1, by = (k >> 1) & 1, bz = k >> 2;
+                const T wk = (bx ? f[0] : T(1) - f[0]) * (by ? f[1] : T(1) - f[1]) *
+                             (bz ? f[2] : T(1) - f[2]);
+                const int tc = t0 + (bz * S + by) * S + bx;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int by = k & 1, bz = k >> 1;
-                for (int e = lo[k]; e < hi[k]; ++e) {
-                    // each term in the state precision (as its offsets and
-                    // ufbar are), the sum in binary64
-                    const vec4 fv = ent[2 * e], uv = ent[2 * e + 1];
-                    const T wk = (e < mid[k] ? fv.x : T(1) - fv.x) * (by ? fv.y : T(1) - fv.y) *
-                                 (bz ? fv.z : T(1) - fv.z);
-                    sum[0] += (double)(wk * uv.x);
-                    sum[1] += (double)(wk * uv.y);
-                    sum[2] += (double)(wk * uv.z);
-                }
+                for (int comp = 0; comp < 3; ++comp)
+                    atomicAdd(&nacc[comp * S3 + tc], (double)(wk * ub[comp]));
             }
-            for (int comp = 0; comp < 3; ++comp) nacc[comp * S3 + n] += sum[comp];
         }
     }
     __syncthreads();
@@ -439,16 +345,16 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_ngp(AdjArgs<T> a)
     __syncthreads();
     const double *lam = a.lamC + c * 3 * E3;
     for (int64_t q = s0 + threadIdx.x; q < s1; q += kAdjBlock) {
-        const int64_t id = a.id[q];
+        const int64_t an = a.id[q];
         const T st[7] = {a.ox[q], a.oy[q], a.oz[q], a.vx[q], a.vy[q], a.vz[q], a.d[q]};
-        if (!adj_live(id, a.count, st)) continue;
+        if (!adj_live(an, a.nrec, st)) continue;
         double rc[7];
-        for (int k = 0; k < 7; ++k) rc[k] = a.adj[8 * id + k];
+        for (int k = 0; k < 7; ++k) rc[k] = a.adj[8 * an + k];
         double ufb[3], fr[3];
         int i0[3], t0;
         reverse_particle<T, E, false>(p, a.dt, tile, lam, st, rc, ufb, i0, fr, t0);
         for (int comp = 0; comp < 3; ++comp) atomicAdd(&ubt[comp * S3 + t0], (T)ufb[comp]);
-        double *rec = a.adj + 8 * id;
+        double *rec = a.adj + 8 * an;
         for (int k = 0; k < 7; ++k) rec[k] = rc[k];
     }
     __syncthreads();
@@ -485,7 +391,72 @@ __global__ void k_zero_f64(double *p, int64_t n)
         p[i] = 0.0;
 }
 
-// dL/dd of every particle out of the adjoint records
+inline int64_t grid_of(int64_t n)
+{
+    const int64_t g = (n + 255) / 256;
+    return g < 1 ? 1 : (g > 16384 ? 16384 : g);
+}
+
+// A checkpoint slot holds a particle when it lies in its chunk's run
+// [base, base + cnt), its id is in [0, count) and it is not a hole (a hole
+// keeps the id of the particle that left it; slots past the runs may hold
+// stale copies of particles).
+template <class T>
+__device__ __forceinline__ bool ck_particle(int32_t id, int64_t count, T ox, T d)
+{
+    return id >= 0 && id < count && ox >= T(0) && d > T(0);
+}
+
+// The checkpoint's particles, a workgroup per chunk: mode 0 replaces the
+// restored store's ids by anchors (every other slot of a run gets -1),
+// mode 1 takes each particle's record from the array by id into the array
+// by anchor, mode 2 puts it back.
+template <class T>
+__global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots, int64_t C,
+                                     int64_t count, int32_t *store_id, double *by_id,
+                                     double *rec, int mode)
+{
+    const T *ox = reinterpret_cast<const T *>(ck + L.state);
+    const T *d = ox + 6 * slots;
+    const int32_t *sid = reinterpret_cast<const int32_t *>(ck + L.id);
+    const int64_t *base = reinterpret_cast<const int64_t *>(ck + L.base);
+    const int32_t *cnt = reinterpret_cast<const int32_t *>(ck + L.cnt);
+    for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const int64_t q0 = base[c], q1 = q0 + cnt[c];
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+            const int32_t k = sid[q];
+            const bool live = ck_particle(k, count, ox[q], d[q]);
+            if (mode == 0) {
+                store_id[q] = live ? (int32_t)q : -1;
+                continue;
+            }
+            if (!live) continue;
+            double2 *ra = reinterpret_cast<double2 *>(rec + 8 * q);
+            double2 *rb = reinterpret_cast<double2 *>(by_id + 8 * (int64_t)k);
+            double2 v[4];
+            if (mode == 1) {
+                for (int j = 0; j < 4; ++j) v[j] = rb[j];
+                for (int j = 0; j < 4; ++j) ra[j] = v[j];
+            } else {
+                for (int j = 0; j < 4; ++j) v[j] = ra[j];
+                for (int j = 0; j < 4; ++j) rb[j] = v[j];
+            }
+        }
+    }
+}
+
+template <class T>
+hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, double *by_id, double *rec,
+                                     int mode, hipStream_t s)
+{
+    const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
+    const int64_t g = c->C < 16384 ? c->C : 16384;
+    hipLaunchKernelGGL((k_checkpoint_records<T>), dim3(g > 0 ? g : 1), dim3(256), 0, s, ck, L,
+                       c->slots, c->C, c->count, (int32_t *)c->store[0][7], by_id, rec, mode);
+    return hipGetLastError();
+}
+
+// dL/dd of every particle out of the adjoint records by id
 __global__ void k_take_dbar(const double *adj, int64_t P, double *dd)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
@@ -493,11 +464,6 @@ __global__ void k_take_dbar(const double *adj, int64_t P, double *dd)
         dd[i] = adj[8 * i + 6];
 }
 
-inline int64_t grid_of(int64_t n)
-{
-    const int64_t g = (n + 255) / 256;
-    return g < 1 ? 1 : (g > 16384 ? 16384 : g);
-}
 
 template <class T>
 AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
@@ -522,7 +488,7 @@ AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const doubl
     a.lamC = lamC;
     a.adj = adj;
     a.Ubar = Ubar;
-    a.count = c->count;
+    a.nrec = c->slots;
     a.p = c->prm;
     a.dt = ts.dt;
     return a;
@@ -564,13 +530,14 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     const size_t sbytes = snapshot_bytes(c);
 
     // one workspace, kept in the context for the next call: the state the
-    // forward run ended in, the saved states of one segment, dL/dS by chunk
-    // and the adjoint records
+    // forward run ended in, the saved states of one segment, dL/dS by chunk,
+    // the adjoint records by id and those of the current segment by anchor
     auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t o_steps = up256(sbytes);
     const size_t o_lam = o_steps + (size_t)K * up256(sbytes);
-    const size_t o_adj = o_lam + up256((size_t)c->C * 3 * E3 * 8);
-    const size_t ws_bytes = o_adj + (size_t)(P > 0 ? P : 1) * 64;
+    const size_t o_rid = o_lam + up256((size_t)c->C * 3 * E3 * 8);
+    const size_t o_adj = o_rid + up256((size_t)(P > 0 ? P : 1) * 64);
+    const size_t ws_bytes = o_adj + (size_t)c->slots * 64;
     if (c->bwd_ws_bytes < ws_bytes) {
         (void)hipFree(c->bwd_ws);
         c->bwd_ws = nullptr;
@@ -583,7 +550,9 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     void *final_state = ws;
     auto step_buf = [&](int64_t k) -> void * { return ws + o_steps + (size_t)k * up256(sbytes); };
     double *lamC = (double *)(ws + o_lam);
+    double *rid = (double *)(ws + o_rid);
     double *adj = (double *)(ws + o_adj);
+    const bool fp64 = c->form == ST_FORM_FP64;
 
     // an error return first drains the stream
     auto fail = [&](hipError_t err) {
@@ -596,14 +565,22 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
                        lamC);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, adj, 8 * P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, rid, 8 * P);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
 
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int64_t k0 = sg * K, k1 = std::min(k0 + K, ntape);
+        // the checkpoint, with anchors in place of its ids, and the records of
+        // its particles by anchor
+        const char *ck = (const char *)c->snaps[(size_t)sg].buf;
         e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
         if (e != hipSuccess) return fail(e);
+        for (int mode = 0; mode < 2; ++mode) {
+            e = fp64 ? launch_checkpoint_records<double>(c, ck, rid, adj, mode, s)
+                     : launch_checkpoint_records<float>(c, ck, rid, adj, mode, s);
+            if (e != hipSuccess) return fail(e);
+        }
         // recompute the segment, each step saving what its reverse reads; the
         // last step's start is the store itself
         for (int64_t k = k0; k < k1; ++k) {
@@ -617,7 +594,7 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
         // and reverse it, newest step first
         for (int64_t k = k1 - 1; k >= k0; --k) {
             const char *snap = (const char *)step_buf(k - k0);
-            if (c->form == ST_FORM_FP64)
+            if (fp64)
                 e = launch_adjoint_step<double>(
                     c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
             else
@@ -625,8 +602,11 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
                     c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
             if (e != hipSuccess) return fail(e);
         }
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, rid, adj, 2, s)
+                 : launch_checkpoint_records<float>(c, ck, rid, adj, 2, s);
+        if (e != hipSuccess) return fail(e);
     }
-    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)adj, P, dd);
+    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)rid, P, dd);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
     e = launch_snapshot(c, final_state, 1, s);
