@@ -52,7 +52,7 @@ struct AdjArgs {
     const int32_t *nitems;
     const T *u;              // field of the step [3][n2][n1][n0]
     const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
-    double *adj;             // adjoint records by anchor, [nrec][8]: xbar[3], ubar[3], dbar, unused
+    T *adj;                  // adjoint records by anchor, [nrec][8]: xbar[3], ubar[3], dbar, unused
     double *Ubar;            // dL/du [3][n2][n1][n0]
     int64_t nrec;            // records (the store's slots)
     Params p;
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
         for (int u = 0; u < PPT; ++u) {
             live[u] = adj_live(an[u], a.nrec, st[u]);
             if (live[u])
-                for (int k = 0; k < 7; ++k) rc[u][k] = a.adj[8 * an[u] + k];
+                for (int k = 0; k < 7; ++k) rc[u][k] = (double)a.adj[8 * an[u] + k];
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -291,8 +291,8 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
             double ufb[3], fr[3];
             int i0[3], t0;
             reverse_particle<T, E, true>(p, a.dt, tile, lam, st[u], rc[u], ufb, i0, fr, t0);
-            double *rec = a.adj + 8 * an[u];
-            for (int k = 0; k < 7; ++k) rec[k] = rc[u][k];
+            T *rec = a.adj + 8 * an[u];
+            for (int k = 0; k < 7; ++k) rec[k] = (T)rc[u][k];
             const T f[3] = {(T)fr[0], (T)fr[1], (T)fr[2]};
             const T ub[3] = {(T)ufb[0], (T)ufb[1], (T)ufb[2]};
 #pragma unroll
@@ -349,13 +349,13 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_ngp(AdjArgs<T> a)
         const T st[7] = {a.ox[q], a.oy[q], a.oz[q], a.vx[q], a.vy[q], a.vz[q], a.d[q]};
         if (!adj_live(an, a.nrec, st)) continue;
         double rc[7];
-        for (int k = 0; k < 7; ++k) rc[k] = a.adj[8 * an + k];
+        for (int k = 0; k < 7; ++k) rc[k] = (double)a.adj[8 * an + k];
         double ufb[3], fr[3];
         int i0[3], t0;
         reverse_particle<T, E, false>(p, a.dt, tile, lam, st, rc, ufb, i0, fr, t0);
         for (int comp = 0; comp < 3; ++comp) atomicAdd(&ubt[comp * S3 + t0], (T)ufb[comp]);
-        double *rec = a.adj + 8 * an;
-        for (int k = 0; k < 7; ++k) rec[k] = rc[k];
+        T *rec = a.adj + 8 * an;
+        for (int k = 0; k < 7; ++k) rec[k] = (T)rc[k];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) {
@@ -413,8 +413,8 @@ __device__ __forceinline__ bool ck_particle(int32_t id, int64_t count, T ox, T d
 // by anchor, mode 2 puts it back.
 template <class T>
 __global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots, int64_t C,
-                                     int64_t count, int32_t *store_id, double *by_id,
-                                     double *rec, int mode)
+                                     int64_t count, int32_t *store_id, T *by_id, T *rec,
+                                     int mode)
 {
     const T *ox = reinterpret_cast<const T *>(ck + L.state);
     const T *d = ox + 6 * slots;
@@ -431,23 +431,25 @@ __global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots
                 continue;
             }
             if (!live) continue;
+            // a record is 8 T: sizeof(T) / 2 pieces of 16 bytes
+            constexpr int NV = (int)sizeof(T) / 2;
             double2 *ra = reinterpret_cast<double2 *>(rec + 8 * q);
             double2 *rb = reinterpret_cast<double2 *>(by_id + 8 * (int64_t)k);
-            double2 v[4];
+            double2 v[NV];
             if (mode == 1) {
-                for (int j = 0; j < 4; ++j) v[j] = rb[j];
-                for (int j = 0; j < 4; ++j) ra[j] = v[j];
+                for (int j = 0; j < NV; ++j) v[j] = rb[j];
+                for (int j = 0; j < NV; ++j) ra[j] = v[j];
             } else {
-                for (int j = 0; j < 4; ++j) v[j] = ra[j];
-                for (int j = 0; j < 4; ++j) rb[j] = v[j];
+                for (int j = 0; j < NV; ++j) v[j] = ra[j];
+                for (int j = 0; j < NV; ++j) rb[j] = v[j];
             }
         }
     }
 }
 
 template <class T>
-hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, double *by_id, double *rec,
-                                     int mode, hipStream_t s)
+hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, T *by_id, T *rec, int mode,
+                                     hipStream_t s)
 {
     const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
     const int64_t g = c->C < 16384 ? c->C : 16384;
@@ -457,17 +459,18 @@ hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, double *by_id, d
 }
 
 // dL/dd of every particle out of the adjoint records by id
-__global__ void k_take_dbar(const double *adj, int64_t P, double *dd)
+template <class T>
+__global__ void k_take_dbar(const T *adj, int64_t P, double *dd)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
          i += (int64_t)gridDim.x * blockDim.x)
-        dd[i] = adj[8 * i + 6];
+        dd[i] = (double)adj[8 * i + 6];
 }
 
 
 template <class T>
 AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
-                    double *adj, double *Ubar)
+                    T *adj, double *Ubar)
 {
     const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
     const T *st = reinterpret_cast<const T *>(snap + L.state);
@@ -536,8 +539,9 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     const size_t o_steps = up256(sbytes);
     const size_t o_lam = o_steps + (size_t)K * up256(sbytes);
     const size_t o_rid = o_lam + up256((size_t)c->C * 3 * E3 * 8);
-    const size_t o_adj = o_rid + up256((size_t)(P > 0 ? P : 1) * 64);
-    const size_t ws_bytes = o_adj + (size_t)c->slots * 64;
+    const size_t rbytes = 8 * c->tsize;   // a record: eight state-precision values
+    const size_t o_adj = o_rid + up256((size_t)(P > 0 ? P : 1) * rbytes);
+    const size_t ws_bytes = o_adj + (size_t)c->slots * rbytes;
     if (c->bwd_ws_bytes < ws_bytes) {
         (void)hipFree(c->bwd_ws);
         c->bwd_ws = nullptr;
@@ -550,8 +554,8 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     void *final_state = ws;
     auto step_buf = [&](int64_t k) -> void * { return ws + o_steps + (size_t)k * up256(sbytes); };
     double *lamC = (double *)(ws + o_lam);
-    double *rid = (double *)(ws + o_rid);
-    double *adj = (double *)(ws + o_adj);
+    void *rid = ws + o_rid;
+    void *adj = ws + o_adj;
     const bool fp64 = c->form == ST_FORM_FP64;
 
     // an error return first drains the stream
@@ -565,7 +569,8 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
                        lamC);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(8 * P)), dim3(256), 0, s, rid, 8 * P);
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(P * (int64_t)c->tsize)), dim3(256), 0, s,
+                       (double *)rid, P * (int64_t)c->tsize);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
 
@@ -577,8 +582,8 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
         e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
         if (e != hipSuccess) return fail(e);
         for (int mode = 0; mode < 2; ++mode) {
-            e = fp64 ? launch_checkpoint_records<double>(c, ck, rid, adj, mode, s)
-                     : launch_checkpoint_records<float>(c, ck, rid, adj, mode, s);
+            e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, mode, s)
+                     : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, mode, s);
             if (e != hipSuccess) return fail(e);
         }
         // recompute the segment, each step saving what its reverse reads; the
@@ -596,17 +601,22 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
             const char *snap = (const char *)step_buf(k - k0);
             if (fp64)
                 e = launch_adjoint_step<double>(
-                    c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
+                    c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, (double *)adj, dU), s);
             else
                 e = launch_adjoint_step<float>(
-                    c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, adj, dU), s);
+                    c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, (float *)adj, dU), s);
             if (e != hipSuccess) return fail(e);
         }
-        e = fp64 ? launch_checkpoint_records<double>(c, ck, rid, adj, 2, s)
-                 : launch_checkpoint_records<float>(c, ck, rid, adj, 2, s);
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, 2, s)
+                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, 2, s);
         if (e != hipSuccess) return fail(e);
     }
-    hipLaunchKernelGGL(k_take_dbar, dim3(grid_of(P)), dim3(256), 0, s, (const double *)rid, P, dd);
+    if (fp64)
+        hipLaunchKernelGGL(k_take_dbar<double>, dim3(grid_of(P)), dim3(256), 0, s,
+                           (const double *)rid, P, dd);
+    else
+        hipLaunchKernelGGL(k_take_dbar<float>, dim3(grid_of(P)), dim3(256), 0, s,
+                           (const float *)rid, P, dd);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(e);
     e = launch_snapshot(c, final_state, 1, s);
