@@ -407,10 +407,11 @@ __device__ __forceinline__ bool ck_particle(int32_t id, int64_t count, T ox, T d
     return id >= 0 && id < count && ox >= T(0) && d > T(0);
 }
 
-// The checkpoint's particles, a workgroup per chunk: mode 0 replaces the
-// restored store's ids by anchors (every other slot of a run gets -1),
-// mode 1 takes each particle's record from the array by id into the array
-// by anchor, mode 2 puts it back.
+// The checkpoint's particles, a workgroup per chunk.  Mode bits: kAnchor
+// replaces the restored store's ids by anchors (every other slot of a run
+// gets -1), kToAnchor takes each particle's record from the array by id into
+// the array by anchor, kToId puts it back.
+constexpr int kAnchor = 1, kToAnchor = 2, kToId = 4;
 template <class T>
 __global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots, int64_t C,
                                      int64_t count, int32_t *store_id, T *by_id, T *rec,
@@ -426,17 +427,14 @@ __global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots
         for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
             const int32_t k = sid[q];
             const bool live = ck_particle(k, count, ox[q], d[q]);
-            if (mode == 0) {
-                store_id[q] = live ? (int32_t)q : -1;
-                continue;
-            }
-            if (!live) continue;
+            if (mode & kAnchor) store_id[q] = live ? (int32_t)q : -1;
+            if (!live || !(mode & (kToAnchor | kToId))) continue;
             // a record is 8 T: sizeof(T) / 2 pieces of 16 bytes
             constexpr int NV = (int)sizeof(T) / 2;
             double2 *ra = reinterpret_cast<double2 *>(rec + 8 * q);
             double2 *rb = reinterpret_cast<double2 *>(by_id + 8 * (int64_t)k);
             double2 v[NV];
-            if (mode == 1) {
+            if (mode & kToAnchor) {
                 for (int j = 0; j < NV; ++j) v[j] = rb[j];
                 for (int j = 0; j < NV; ++j) ra[j] = v[j];
             } else {
@@ -472,21 +470,36 @@ template <class T>
 AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
                     T *adj, double *Ubar)
 {
-    const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
-    const T *st = reinterpret_cast<const T *>(snap + L.state);
     AdjArgs<T> a;
-    a.ox = st;
-    a.oy = st + c->slots;
-    a.oz = st + 2 * c->slots;
-    a.vx = st + 3 * c->slots;
-    a.vy = st + 4 * c->slots;
-    a.vz = st + 5 * c->slots;
-    a.d = st + 6 * c->slots;
-    a.id = reinterpret_cast<const int32_t *>(snap + L.id);
-    a.base = reinterpret_cast<const int64_t *>(snap + L.base);
-    a.cnt = reinterpret_cast<const int32_t *>(snap + L.cnt);
-    a.items = reinterpret_cast<const int32_t *>(snap + L.items);
-    a.nitems = reinterpret_cast<const int32_t *>(snap + L.nitems);
+    if (snap) {
+        const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
+        const T *st = reinterpret_cast<const T *>(snap + L.state);
+        a.ox = st;
+        a.oy = st + c->slots;
+        a.oz = st + 2 * c->slots;
+        a.vx = st + 3 * c->slots;
+        a.vy = st + 4 * c->slots;
+        a.vz = st + 5 * c->slots;
+        a.d = st + 6 * c->slots;
+        a.id = reinterpret_cast<const int32_t *>(snap + L.id);
+        a.base = reinterpret_cast<const int64_t *>(snap + L.base);
+        a.cnt = reinterpret_cast<const int32_t *>(snap + L.cnt);
+        a.items = reinterpret_cast<const int32_t *>(snap + L.items);
+        a.nitems = reinterpret_cast<const int32_t *>(snap + L.nitems);
+    } else {   // the store itself, with its layout and work items
+        a.ox = (const T *)c->store[0][0];
+        a.oy = (const T *)c->store[0][1];
+        a.oz = (const T *)c->store[0][2];
+        a.vx = (const T *)c->store[0][3];
+        a.vy = (const T *)c->store[0][4];
+        a.vz = (const T *)c->store[0][5];
+        a.d = (const T *)c->store[0][6];
+        a.id = (const int32_t *)c->store[0][7];
+        a.base = c->base;
+        a.cnt = c->cnt;
+        a.items = c->items;
+        a.nitems = c->flags + F_NITEMS;
+    }
     a.u = reinterpret_cast<const T *>(ts.u);
     a.lamC = lamC;
     a.adj = adj;
@@ -581,24 +594,20 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
         const char *ck = (const char *)c->snaps[(size_t)sg].buf;
         e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
         if (e != hipSuccess) return fail(e);
-        for (int mode = 0; mode < 2; ++mode) {
-            e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, mode, s)
-                     : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, mode, s);
-            if (e != hipSuccess) return fail(e);
-        }
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj,
+                                                     kAnchor | kToAnchor, s)
+                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj,
+                                                    kAnchor | kToAnchor, s);
+        if (e != hipSuccess) return fail(e);
         // recompute the segment, each step saving what its reverse reads; the
-        // last step's start is the store itself
-        for (int64_t k = k0; k < k1; ++k) {
-            void *save = step_buf(k - k0);
-            if (k + 1 < k1)
-                e = launch_step(c, c->tape[(size_t)k].u, c->tape[(size_t)k].dt, 0, s, save);
-            else
-                e = launch_snapshot(c, save, 0, s);
+        // last step's start is the store itself, reversed from there
+        for (int64_t k = k0; k + 1 < k1; ++k) {
+            e = launch_step(c, c->tape[(size_t)k].u, c->tape[(size_t)k].dt, 0, s, step_buf(k - k0));
             if (e != hipSuccess) return fail(e);
         }
         // and reverse it, newest step first
         for (int64_t k = k1 - 1; k >= k0; --k) {
-            const char *snap = (const char *)step_buf(k - k0);
+            const char *snap = k + 1 < k1 ? (const char *)step_buf(k - k0) : nullptr;
             if (fp64)
                 e = launch_adjoint_step<double>(
                     c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, (double *)adj, dU), s);
@@ -607,8 +616,8 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
                     c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, (float *)adj, dU), s);
             if (e != hipSuccess) return fail(e);
         }
-        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, 2, s)
-                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, 2, s);
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, kToId, s)
+                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, kToId, s);
         if (e != hipSuccess) return fail(e);
     }
     if (fp64)
