@@ -283,9 +283,10 @@ def leg_adjoint(pkg, torch, np, synth):
            "dL_dd": float((dd - dd64).norm() / dd64.norm())}
     value = w.P * w.nsteps / ((fwd_ms + bwd_ms) / 1e3)
     # byte model of forward + adjoint with recomputation, per particle-step:
-    # forward 52, recompute with the saved state 52 + 24, reverse 28 (saved
-    # state) + 48 (position and velocity adjoints) + 8 (diameter adjoint) + 4
-    model_b = 216
+    # forward 52; recompute 52 + 32 (the saved state, 28, and its anchor, 4);
+    # reverse 28 (saved state) + 4 (anchor) + 56 (the seven binary32 adjoint
+    # values, xbar, ubar and dbar, read and written)
+    model_b = 224
     return {"workload": w.name, "particles": w.P, "steps": w.nsteps, "checkpoint_every": 20,
             "value": value, "unit": "particle-steps/s",
             "model_bytes_per_particle_step": model_b,

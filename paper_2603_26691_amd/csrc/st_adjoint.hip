@@ -60,9 +60,9 @@ struct AdjArgs {
 };
 
 // One workgroup of 256 threads per work item, two particles per thread and
-// pass (one per pass, 384-thread groups at three waves per SIMD, three or
-// four per pass, and the next pass's loads issued during the current one
-// measured no faster).
+// pass (one per pass, 384-thread groups at three waves per SIMD, three per
+// pass, the next pass's loads issued during the current one, and a pass's
+// LDS atomics issued after all its reverses measured no faster).
 constexpr int kAdjBlock = 256;
 constexpr int kAdjPPT = 2;
 
@@ -226,8 +226,8 @@ __device__ __forceinline__ void reverse_particle(const Params &p, double dt, con
     rc[6] += (2.0 * taubar * tau + Rebar * Re + 3.0 * mbar * mass) / dp;
 }
 
-// Trilinear: one workgroup per work item.  Each thread reverses kAdjPPT
-// particles per pass, their loads issued together (saved states and anchors
+// Trilinear: one workgroup per work item.  Each thread reverses up to
+// kAdjPPT particles per pass, their loads issued together (saved states and anchors
 // first, then the records the anchors address), and adds each particle's
 // eight weighted ufbar terms to the tile's node sums in LDS: each term formed
 // in the state precision from the particle's stencil offsets and ufbar
@@ -259,7 +259,14 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
     __syncthreads();
     const double *lam = a.lamC + c * 3 * E3;
 
-    for (int64_t q0 = s0; q0 < s1; q0 += PPT * kAdjBlock) {
+    // a thread takes the slots s0 + threadIdx.x + j kAdjBlock, PPT values of
+    // j per pass; in binary32 the odd waves take a single one in their first
+    // pass, so that the waves' loads and LDS atomics fall out of step
+    const bool shift = sizeof(T) == 4 && ((threadIdx.x >> 6) & 1);
+    for (int64_t j = 0, first = 1; s0 + j * kAdjBlock < s1; first = 0) {
+        const int np = (first && shift) ? 1 : PPT;
+        const int64_t q0 = s0 + j * kAdjBlock;
+        j += np;
         int64_t an[PPT];
         T st[PPT][7];
         double rc[PPT][7];
@@ -267,7 +274,7 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
         for (int u = 0; u < PPT; ++u) {
             const int64_t q = q0 + threadIdx.x + (int64_t)u * kAdjBlock;
             an[u] = -1;
-            if (q < s1) {
+            if (u < np && q < s1) {
                 an[u] = a.id[q];
                 st[u][0] = a.ox[q];
                 st[u][1] = a.oy[q];
