@@ -401,13 +401,18 @@ __device__ __forceinline__ void write_items(const ItemArgs &a, int64_t c)
     write_items_at(a, c, a.noff[c], a.noff[c + 1]);
 }
 
-__device__ __forceinline__ void finish_flags(const ItemArgs &a)
+__device__ __forceinline__ void finish_flags_n(const ItemArgs &a, int32_t nitems)
 {
-    a.flags[F_NITEMS] = a.noff[a.C];
+    a.flags[F_NITEMS] = nitems;
     a.flags[F_LASTMOV] = a.flags[nmov_slot(a.epoch)];
     a.flags[nmov_slot(a.epoch + 1)] = 0;
     // holes are streamed like particles until a full re-bin drops them
     if (a.flags[F_DEAD] > a.dead_limit) a.flags[F_FORCE] = a.epoch + 1;
+}
+
+__device__ __forceinline__ void finish_flags(const ItemArgs &a)
+{
+    finish_flags_n(a, a.noff[a.C]);
 }
 
 // one workgroup: scan, items and reset (C <= kScan1Max)
@@ -432,6 +437,14 @@ __global__ void k_items(ItemArgs a)
 // took the top min(h, in) holes and the rest of them extended the chunk;
 // holes no arrival took stay listed (and marked: a -1 offset or a negated
 // diameter).  Returns the chunk's holes.
+// chunk c's slot count after the arrivals (as count_chunk_from sets it)
+__device__ __forceinline__ int32_t chunk_count_after(int32_t out, int32_t in, int32_t nd,
+                                                     int32_t cnt)
+{
+    const int32_t h = nd + out;
+    return in >= h ? cnt + in - h : cnt;
+}
+
 template <class T>
 __device__ __forceinline__ int32_t count_chunk_from(const View<T> &V, int32_t out, int32_t in,
                                                     int32_t nd, int32_t cnt, int64_t c)
@@ -461,7 +474,7 @@ __device__ __forceinline__ int32_t count_chunk(const View<T> &V, const int32_t *
 // re-keyed counts; the scatter still walks the current items, so the commit
 // writes the new ones.
 template <class T>
-__global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, Segments now,
+__global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase,
                                                   Segments rekeyed, ItemArgs a, View<T> V,
                                                   const int32_t *flags)
 {
@@ -472,8 +485,9 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
         block_scan_all<int32_t>(rekeyed, a.C, a.noff);
         return;
     }
-    // a thread's chunks (at most kScan1Max / 1024): every load is issued
-    // before the first store, so that the latencies overlap
+    // a thread's chunks c = k 1024 + threadIdx.x (at most kScan1Max / 1024):
+    // every load is issued before the first store, so that the latencies
+    // overlap, and the new counts, item offsets and totals stay in registers
     constexpr int PT = kScan1Max / 1024;
     int32_t out[PT], in[PT], nd[PT], cn[PT];
 #pragma unroll
@@ -487,33 +501,37 @@ __global__ void __launch_bounds__(1024) k_layout1(Rooms rooms, int64_t *nbase, S
             cn[k] = V.cnt[c];
         }
     }
-    int32_t dead = 0;
+    int32_t dead = 0, nseg[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
         const int64_t c = k * 1024 + threadIdx.x;
-        if (c < a.C) dead += count_chunk_from(V, out[k], in[k], nd[k], cn[k], c);
-    }
-    int32_t total;
-    block_excl_scan<int32_t>(dead, total);   // ends with a barrier: the counts are visible
-    if (threadIdx.x == 0) a.flags[F_DEAD] = total;
-    block_scan_all<int32_t>(now, a.C, a.noff);
-    __syncthreads();
-    int32_t o[PT], e[PT];
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        const int64_t c = k * 1024 + threadIdx.x;
-        o[k] = e[k] = 0;
+        nseg[k] = 0;
         if (c < a.C) {
-            o[k] = a.noff[c];
-            e[k] = a.noff[c + 1];
+            dead += count_chunk_from(V, out[k], in[k], nd[k], cn[k], c);
+            nseg[k] = (chunk_count_after(out[k], in[k], nd[k], cn[k]) + kSeg - 1) / kSeg;
         }
     }
+    int32_t total;
+    block_excl_scan<int32_t>(dead, total);
+    if (threadIdx.x == 0) a.flags[F_DEAD] = total;
+    // the item offsets in chunk order, a round of 1024 chunks at a time
+    int32_t carry = 0;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
+        if ((int64_t)k * 1024 >= a.C) break;   // uniform
+        int32_t rt;
+        const int32_t o = carry + block_excl_scan<int32_t>(nseg[k], rt);
         const int64_t c = k * 1024 + threadIdx.x;
-        if (c < a.C) write_items_at(a, c, o[k], e[k]);
+        if (c < a.C) {
+            a.noff[c] = o;
+            write_items_at(a, c, o, o + nseg[k]);
+        }
+        carry += rt;
     }
-    if (threadIdx.x == 0) finish_flags(a);
+    if (threadIdx.x == 0) {
+        a.noff[a.C] = carry;
+        finish_flags_n(a, carry);
+    }
 }
 
 __global__ void k_set_flag(int32_t *flags, int which, int32_t v) { flags[which] = v; }
@@ -1249,17 +1267,39 @@ template <class T>
 __device__ void arrive(const RebinArgs<T> &a)
 {
     const View<T> &V = a.V;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // a thread's first mover is read together with the count (the list's
+    // entries below its capacity can all be read), each next one while the
+    // current one is placed
+    int32_t c = 0, r = 0;
+    MoverRec<T> rec{};
+    if (m < a.mcap) {
+        c = a.mv.dest[m];
+        r = a.mv.rank[m];
+        rec = a.mv.rec[m];
+    }
     const int64_t nm = a.flags[nmov_slot(a.epoch)];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[F_DEAD] = 0;   // summed by the counts
-    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < nm;
-         m += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = a.mv.dest[m];
-        const int32_t r = a.mv.rank[m];
+    for (; m < nm; m += stride) {
         const int64_t base = V.base[c];
         const int32_t h = V.ndead[c] + a.out_cnt[c];
         const int64_t slot = r < h ? base + a.hole[base + h - 1 - r]
                                    : base + V.cnt[c] + (r - h);
-        place_mover(V, slot, a.mv, m);
+        const MoverRec<T> cur = rec;
+        if (m + stride < nm && m + stride < a.mcap) {
+            c = a.mv.dest[m + stride];
+            r = a.mv.rank[m + stride];
+            rec = a.mv.rec[m + stride];
+        }
+        V.ox[slot] = cur.ox;
+        V.oy[slot] = cur.oy;
+        V.oz[slot] = cur.oz;
+        V.vx[slot] = cur.vx;
+        V.vy[slot] = cur.vy;
+        V.vz[slot] = cur.vz;
+        V.d[slot] = cur.d;
+        V.id[slot] = cur.id;
     }
 }
 
@@ -1744,7 +1784,7 @@ hipError_t launch_rebin(st_ctx *c, int64_t npend, hipStream_t s)
     if (C <= kScan1Max) {
         // counts, rooms (when due) and the next items in one workgroup
         hipLaunchKernelGGL((k_layout1<T>), dim3(1), dim3(1024), 0, s, rooms, c->nbase,
-                           Segments{c->cnt}, Segments{c->new_cnt}, ia, a.V, c->flags);
+                           Segments{c->new_cnt}, ia, a.V, c->flags);
         hipLaunchKernelGGL((k_rekey_scatter<T>), dim3(gs), dim3(256), 0, s, a);
         hipLaunchKernelGGL((k_rekey_commit<T>), dim3(grid_for(c->slots, 2048)), dim3(256), 0, s,
                            a, ia, 1);
