@@ -184,10 +184,13 @@ st_status st_get_particles(st_ctx *ctx, double *x, double *up, double *d,
  * dL/dd (device, [count] binary64, by id; may be NULL when count is 0).
  * Checkpoints are restored and
  * the steps between them recomputed.  The tape is consumed; its checkpoint
- * buffers and the call's workspace (about tape + 2 copies of the particle
- * store plus 64 bytes per particle) stay allocated for the next taped run
- * until st_tape_clear or st_destroy.  Returns when the results are written
- * (the call synchronises hip_stream).  ST_ERR_STATE if nothing is taped. */
+ * buffers and the call's workspace (about tape + 1 copies of the particle
+ * store, plus the adjoint records: 8 values of the state precision per
+ * particle and per slot) stay allocated for the next taped run until
+ * st_tape_clear or st_destroy.  Returns when the results are written and the
+ * store holds the state the taped run ended in (the call synchronises
+ * hip_stream); after a HIP error the store's contents are undefined.
+ * ST_ERR_STATE if nothing is taped. */
 st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,
                       double *dL_dd, void *hip_stream);
 
