@@ -54,6 +54,7 @@ struct AdjArgs {
     const double *lamC;      // dL/dSu_int by chunk [C][3][E^3]
     T *adj;                  // adjoint records by anchor, [nrec][8]: xbar[3], ubar[3], dbar, unused
     double *Ubar;            // dL/du [3][n2][n1][n0]
+    double *tacc;            // per-chunk tile sums of dL/du over the steps, [C][3][S3], or null
     int64_t nrec;            // records (the store's slots)
     Params p;
     double dt;
@@ -254,8 +255,14 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
     const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
     const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
 
+    // a chunk that is one work item is this workgroup's alone: its node sums
+    // continue those of the steps reversed before (kept per chunk), and go
+    // back to them at the end; a chunk split over several items adds its
+    // sums to dL/du atomically
+    const bool own = a.tacc != nullptr && a.cnt[c] <= kSeg;
+    double *const tacc_c = own ? a.tacc + c * 3 * S3 : nullptr;
     stage_tile<T, E, kAdjBlock>(p, a.u, cx, cy, cz, tile);
-    for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) nacc[t] = 0.0;
+    for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) nacc[t] = own ? tacc_c[t] : 0.0;
     __syncthreads();
     const double *lam = a.lamC + c * 3 * E3;
 
@@ -315,11 +322,37 @@ __global__ void __launch_bounds__(kAdjBlock, 2) k_adjoint_tri(AdjArgs<T> a)
         }
     }
     __syncthreads();
+    if (own) {
+        for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) tacc_c[t] = nacc[t];
+        return;
+    }
     for (int n = threadIdx.x; n < S3; n += kAdjBlock) {
         const int64_t g = tile_cell<E>(p, cx, cy, cz, n);
         for (int comp = 0; comp < 3; ++comp) {
             const double v = nacc[comp * S3 + n];
             if (v != 0.0) atomicAdd(a.Ubar + comp * ncell + g, v);
+        }
+    }
+}
+
+// The per-chunk tile sums into dL/du, one atomic add per nonzero node and
+// component (after the last reversed step).
+template <int E>
+__global__ void k_fold_tiles(const double *tacc, Params p, int64_t C, double *Ubar)
+{
+    constexpr int S = E + 2;
+    constexpr int S3 = S * S * S;
+    const int64_t ncell = (int64_t)p.n[0] * p.n[1] * p.n[2];
+    for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
+        const int cx = (int)(c % p.nc[0]);
+        const int cy = (int)((c / p.nc[0]) % p.nc[1]);
+        const int cz = (int)(c / ((int64_t)p.nc[0] * p.nc[1]));
+        for (int n = threadIdx.x; n < S3; n += blockDim.x) {
+            const int64_t g = tile_cell<E>(p, cx, cy, cz, n);
+            for (int comp = 0; comp < 3; ++comp) {
+                const double v = tacc[(c * 3 + comp) * S3 + n];
+                if (v != 0.0) atomicAdd(Ubar + comp * ncell + g, v);
+            }
         }
     }
 }
@@ -475,7 +508,7 @@ __global__ void k_take_dbar(const T *adj, int64_t P, double *dd)
 
 template <class T>
 AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const double *lamC,
-                    T *adj, double *Ubar)
+                    T *adj, double *Ubar, double *tacc)
 {
     AdjArgs<T> a;
     if (snap) {
@@ -511,6 +544,7 @@ AdjArgs<T> adj_args(st_ctx *c, const char *snap, const TapeStep &ts, const doubl
     a.lamC = lamC;
     a.adj = adj;
     a.Ubar = Ubar;
+    a.tacc = tacc;
     a.nrec = c->slots;
     a.p = c->prm;
     a.dt = ts.dt;
@@ -561,7 +595,13 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     const size_t o_rid = o_lam + up256((size_t)c->C * 3 * E3 * 8);
     const size_t rbytes = 8 * c->tsize;   // a record: eight state-precision values
     const size_t o_adj = o_rid + up256((size_t)(P > 0 ? P : 1) * rbytes);
-    const size_t ws_bytes = o_adj + (size_t)c->slots * rbytes;
+    // the trilinear kernel's per-chunk tile sums of dL/du, when they fit in
+    // a GiB (else each step adds its sums to dL/du atomically)
+    const int64_t S3 = (int64_t)(c->prm.E + 2) * (c->prm.E + 2) * (c->prm.E + 2);
+    const size_t tbytes = (size_t)c->C * 3 * S3 * 8;
+    const bool use_tacc = c->prm.interp == 0 && tbytes <= ((size_t)1 << 30);
+    const size_t o_tacc = o_adj + up256((size_t)c->slots * rbytes);
+    const size_t ws_bytes = o_tacc + (use_tacc ? tbytes : 0);
     if (c->bwd_ws_bytes < ws_bytes) {
         (void)hipFree(c->bwd_ws);
         c->bwd_ws = nullptr;
@@ -576,6 +616,7 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     double *lamC = (double *)(ws + o_lam);
     void *rid = ws + o_rid;
     void *adj = ws + o_adj;
+    double *tacc = use_tacc ? (double *)(ws + o_tacc) : nullptr;
     const bool fp64 = c->form == ST_FORM_FP64;
 
     // an error return first drains the stream
@@ -589,6 +630,9 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     hipLaunchKernelGGL(k_lambda_to_chunks, dim3(grid_of(3 * ncell)), dim3(256), 0, s, lam, c->prm,
                        lamC);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
+    if (tacc)
+        hipLaunchKernelGGL(k_zero_f64, dim3(grid_of((int64_t)(tbytes / 8))), dim3(256), 0, s,
+                           tacc, (int64_t)(tbytes / 8));
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(P * (int64_t)c->tsize)), dim3(256), 0, s,
                        (double *)rid, P * (int64_t)c->tsize);
     e = hipGetLastError();
@@ -617,15 +661,25 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
             const char *snap = k + 1 < k1 ? (const char *)step_buf(k - k0) : nullptr;
             if (fp64)
                 e = launch_adjoint_step<double>(
-                    c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, (double *)adj, dU), s);
+                    c, adj_args<double>(c, snap, c->tape[(size_t)k], lamC, (double *)adj, dU,
+                                          tacc), s);
             else
                 e = launch_adjoint_step<float>(
-                    c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, (float *)adj, dU), s);
+                    c, adj_args<float>(c, snap, c->tape[(size_t)k], lamC, (float *)adj, dU,
+                                         tacc), s);
             if (e != hipSuccess) return fail(e);
         }
         e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, kToId, s)
                  : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, kToId, s);
         if (e != hipSuccess) return fail(e);
+    }
+    if (tacc) {
+        const dim3 g(std::min<int64_t>(c->C, 16384));
+        switch (c->prm.E) {
+        case 2: hipLaunchKernelGGL(k_fold_tiles<2>, g, dim3(256), 0, s, tacc, c->prm, c->C, dU); break;
+        case 4: hipLaunchKernelGGL(k_fold_tiles<4>, g, dim3(256), 0, s, tacc, c->prm, c->C, dU); break;
+        default: hipLaunchKernelGGL(k_fold_tiles<8>, g, dim3(256), 0, s, tacc, c->prm, c->C, dU); break;
+        }
     }
     if (fp64)
         hipLaunchKernelGGL(k_take_dbar<double>, dim3(grid_of(P)), dim3(256), 0, s,
