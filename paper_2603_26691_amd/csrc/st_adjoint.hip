@@ -450,25 +450,38 @@ __device__ __forceinline__ bool ck_particle(int32_t id, int64_t count, T ox, T d
 // The checkpoint's particles, a workgroup per chunk.  Mode bits: kAnchor
 // replaces the restored store's ids by anchors (every other slot of a run
 // gets -1), kToAnchor takes each particle's record from the array by id into
-// the array by anchor, kToId puts it back.
+// the array by anchor, kToId puts it back.  With a second checkpoint (ok,
+// the neighbouring segment's), only the particles that it does not hold at
+// the same slot of the same chunk's run move: their records change place
+// between the two segments' arrays by anchor, which are one array, so the
+// others' records are already where the next segment reads them.
 constexpr int kAnchor = 1, kToAnchor = 2, kToId = 4;
 template <class T>
-__global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots, int64_t C,
-                                     int64_t count, int32_t *store_id, T *by_id, T *rec,
-                                     int mode)
+__global__ void k_checkpoint_records(const char *ck, const char *ok, SnapLayout L, int64_t slots,
+                                     int64_t C, int64_t count, int32_t *store_id, T *by_id,
+                                     T *rec, int mode)
 {
     const T *ox = reinterpret_cast<const T *>(ck + L.state);
     const T *d = ox + 6 * slots;
     const int32_t *sid = reinterpret_cast<const int32_t *>(ck + L.id);
     const int64_t *base = reinterpret_cast<const int64_t *>(ck + L.base);
     const int32_t *cnt = reinterpret_cast<const int32_t *>(ck + L.cnt);
+    const char *const oc = ok ? ok : ck;   // (not read without ok)
+    const T *o_ox = reinterpret_cast<const T *>(oc + L.state);
+    const T *o_d = o_ox + 6 * slots;
+    const int32_t *o_sid = reinterpret_cast<const int32_t *>(oc + L.id);
+    const int64_t *o_base = reinterpret_cast<const int64_t *>(oc + L.base);
+    const int32_t *o_cnt = reinterpret_cast<const int32_t *>(oc + L.cnt);
     for (int64_t c = blockIdx.x; c < C; c += gridDim.x) {
         const int64_t q0 = base[c], q1 = q0 + cnt[c];
+        const int64_t p0 = ok ? o_base[c] : 0, p1 = ok ? p0 + o_cnt[c] : 0;
         for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
             const int32_t k = sid[q];
             const bool live = ck_particle(k, count, ox[q], d[q]);
             if (mode & kAnchor) store_id[q] = live ? (int32_t)q : -1;
             if (!live || !(mode & (kToAnchor | kToId))) continue;
+            if (ok && q >= p0 && q < p1 && o_sid[q] == k && ck_particle(k, count, o_ox[q], o_d[q]))
+                continue;   // the same slot in both
             // a record is 8 T: sizeof(T) / 2 pieces of 16 bytes
             constexpr int NV = (int)sizeof(T) / 2;
             double2 *ra = reinterpret_cast<double2 *>(rec + 8 * q);
@@ -486,13 +499,13 @@ __global__ void k_checkpoint_records(const char *ck, SnapLayout L, int64_t slots
 }
 
 template <class T>
-hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, T *by_id, T *rec, int mode,
-                                     hipStream_t s)
+hipError_t launch_checkpoint_records(st_ctx *c, const char *ck, const char *ok, T *by_id,
+                                     T *rec, int mode, hipStream_t s)
 {
     const SnapLayout L = snap_layout(c->slots, c->tsize, c->C, c->max_items);
     const int64_t g = c->C < 16384 ? c->C : 16384;
-    hipLaunchKernelGGL((k_checkpoint_records<T>), dim3(g > 0 ? g : 1), dim3(256), 0, s, ck, L,
-                       c->slots, c->C, c->count, (int32_t *)c->store[0][7], by_id, rec, mode);
+    hipLaunchKernelGGL((k_checkpoint_records<T>), dim3(g > 0 ? g : 1), dim3(256), 0, s, ck, ok,
+                       L, c->slots, c->C, c->count, (int32_t *)c->store[0][7], by_id, rec, mode);
     return hipGetLastError();
 }
 
@@ -641,13 +654,16 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     for (int64_t sg = nseg - 1; sg >= 0; --sg) {
         const int64_t k0 = sg * K, k1 = std::min(k0 + K, ntape);
         // the checkpoint, with anchors in place of its ids, and the records of
-        // its particles by anchor
+        // its particles by anchor (those the later checkpoint held at the
+        // same slot are there already)
         const char *ck = (const char *)c->snaps[(size_t)sg].buf;
+        const char *later = sg + 1 < nseg ? (const char *)c->snaps[(size_t)sg + 1].buf : nullptr;
+        const char *earlier = sg > 0 ? (const char *)c->snaps[(size_t)sg - 1].buf : nullptr;
         e = launch_snapshot(c, c->snaps[(size_t)sg].buf, 1, s);
         if (e != hipSuccess) return fail(e);
-        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj,
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, later, (double *)rid, (double *)adj,
                                                      kAnchor | kToAnchor, s)
-                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj,
+                 : launch_checkpoint_records<float>(c, ck, later, (float *)rid, (float *)adj,
                                                     kAnchor | kToAnchor, s);
         if (e != hipSuccess) return fail(e);
         // recompute the segment, each step saving what its reverse reads; the
@@ -669,8 +685,12 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
                                          tacc), s);
             if (e != hipSuccess) return fail(e);
         }
-        e = fp64 ? launch_checkpoint_records<double>(c, ck, (double *)rid, (double *)adj, kToId, s)
-                 : launch_checkpoint_records<float>(c, ck, (float *)rid, (float *)adj, kToId, s);
+        // the records of the particles the earlier checkpoint does not hold at
+        // the same slot (after the first segment, all) go to the array by id
+        e = fp64 ? launch_checkpoint_records<double>(c, ck, earlier, (double *)rid, (double *)adj,
+                                                     kToId, s)
+                 : launch_checkpoint_records<float>(c, ck, earlier, (float *)rid, (float *)adj,
+                                                    kToId, s);
         if (e != hipSuccess) return fail(e);
     }
     if (tacc) {
