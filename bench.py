@@ -255,6 +255,9 @@ def leg_adjoint(pkg, torch, np, synth):
     def run(form, Uf, lam_given=None):
         t = make_tracker(pkg, w, form)
         inject_host(t, w)
+        # the checkpoint buffers and the backward's workspace are allocated
+        # with the tracker, before the timed region
+        t.tape_reserve(20, w.nsteps)
         torch.cuda.synchronize()
         e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         e0.record()

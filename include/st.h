@@ -198,6 +198,17 @@ st_status st_backward(st_ctx *ctx, const double *dL_dSint, double *dL_du,
  * differentiating, and releases the buffers st_backward keeps. */
 st_status st_tape_clear(st_ctx *ctx);
 
+/* Outside the paper (see st_backward).  Allocates ahead of time what a taped
+ * run of `substeps` sub-steps with a checkpoint every `tape` sub-steps and
+ * its st_backward need (the checkpoint buffers and the backward's workspace,
+ * for the particles held now), so that neither st_step nor st_backward
+ * allocates during that run: for callers that time or capture it.  The
+ * buffers are kept like those of a consumed tape (released by st_tape_clear
+ * or st_destroy).  ST_ERR_INVALID for tape <= 0, substeps < 0 or the FP32
+ * everywhere form (which is not taped), ST_ERR_STATE while a tape is
+ * recorded, ST_ERR_OOM when the device memory runs out. */
+st_status st_tape_reserve(st_ctx *ctx, int32_t tape, int64_t substeps);
+
 /* Paper Sec. 2.3 (asynchronous coupling; the Eulerian and Lagrangian phases
  * at most one time step apart) and Sec. 2.5 (the lag of one step).  On one
  * GPU the Eulerian update is a synthetic field rotation on a second stream.

@@ -58,6 +58,7 @@ SIGNATURES = {
     "st_get_particles": (_I, [_P, _P, _P, _P, _P, _P, _I, _P]),
     "st_backward": (_I, [_P, _P, _P, _P, _P]),
     "st_tape_clear": (_I, [_P]),
+    "st_tape_reserve": (_I, [_P, _I32, _I64]),
     "st_run_coupled": (_I, [_P, _P, _P, _I32, _D, ctypes.POINTER(ctypes.c_float),
                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _P]),
     "st_stats": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),

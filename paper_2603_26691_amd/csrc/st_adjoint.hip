@@ -588,6 +588,58 @@ hipError_t launch_adjoint_step(st_ctx *c, const AdjArgs<T> &a, hipStream_t s)
 
 }  // namespace
 
+namespace {
+
+// One workspace, kept in the context for the next call: the state the
+// forward run ended in, the saved states of one segment (K - 1 steps; the
+// newest is the store itself), dL/dS by chunk, the adjoint records by id and
+// those of the current segment by anchor, and the trilinear kernel's
+// per-chunk tile sums of dL/du when they fit in a GiB (else each step adds
+// its sums to dL/du atomically).
+struct BwdLayout {
+    size_t step_bytes, o_steps, o_lam, o_rid, o_adj, o_tacc, tbytes, bytes;
+};
+
+BwdLayout bwd_layout(const st_ctx *c, int64_t K)
+{
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const int64_t P = c->count;
+    const int64_t E3 = (int64_t)c->prm.E * c->prm.E * c->prm.E;
+    const int64_t S3 = (int64_t)(c->prm.E + 2) * (c->prm.E + 2) * (c->prm.E + 2);
+    const size_t rbytes = 8 * c->tsize;   // a record: eight state-precision values
+    BwdLayout W;
+    W.step_bytes = up256(snapshot_bytes(c));
+    W.o_steps = W.step_bytes;
+    W.o_lam = W.o_steps + (size_t)(K > 1 ? K - 1 : 0) * W.step_bytes;
+    W.o_rid = W.o_lam + up256((size_t)c->C * 3 * E3 * 8);
+    W.o_adj = W.o_rid + up256((size_t)(P > 0 ? P : 1) * rbytes);
+    W.o_tacc = W.o_adj + up256((size_t)c->slots * rbytes);
+    W.tbytes = (size_t)c->C * 3 * S3 * 8;
+    if (c->prm.interp != 0 || W.tbytes > ((size_t)1 << 30)) W.tbytes = 0;
+    W.bytes = W.o_tacc + W.tbytes;
+    return W;
+}
+
+hipError_t ensure_bwd_workspace(st_ctx *c, const BwdLayout &W)
+{
+    if (c->bwd_ws_bytes >= W.bytes) return hipSuccess;
+    (void)hipFree(c->bwd_ws);
+    c->bwd_ws = nullptr;
+    c->bwd_ws_bytes = 0;
+    hipError_t e = hipMalloc(&c->bwd_ws, W.bytes);
+    if (e != hipSuccess) return e;
+    c->bwd_ws_bytes = W.bytes;
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t reserve_backward(st_ctx *c, int64_t K)
+{
+    if (K <= 0) return hipErrorInvalidValue;
+    return ensure_bwd_workspace(c, bwd_layout(c, K));
+}
+
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s)
 {
     const int64_t ntape = (int64_t)c->tape.size();
@@ -596,40 +648,17 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
     if (ntape == 0 || K <= 0 || nseg != (ntape + K - 1) / K) return hipErrorInvalidValue;
     const int64_t P = c->count;
     const int64_t ncell = (int64_t)c->prm.n[0] * c->prm.n[1] * c->prm.n[2];
-    const int64_t E3 = (int64_t)c->prm.E * c->prm.E * c->prm.E;
-    const size_t sbytes = snapshot_bytes(c);
 
-    // one workspace, kept in the context for the next call: the state the
-    // forward run ended in, the saved states of one segment, dL/dS by chunk,
-    // the adjoint records by id and those of the current segment by anchor
-    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    const size_t o_steps = up256(sbytes);
-    const size_t o_lam = o_steps + (size_t)K * up256(sbytes);
-    const size_t o_rid = o_lam + up256((size_t)c->C * 3 * E3 * 8);
-    const size_t rbytes = 8 * c->tsize;   // a record: eight state-precision values
-    const size_t o_adj = o_rid + up256((size_t)(P > 0 ? P : 1) * rbytes);
-    // the trilinear kernel's per-chunk tile sums of dL/du, when they fit in
-    // a GiB (else each step adds its sums to dL/du atomically)
-    const int64_t S3 = (int64_t)(c->prm.E + 2) * (c->prm.E + 2) * (c->prm.E + 2);
-    const size_t tbytes = (size_t)c->C * 3 * S3 * 8;
-    const bool use_tacc = c->prm.interp == 0 && tbytes <= ((size_t)1 << 30);
-    const size_t o_tacc = o_adj + up256((size_t)c->slots * rbytes);
-    const size_t ws_bytes = o_tacc + (use_tacc ? tbytes : 0);
-    if (c->bwd_ws_bytes < ws_bytes) {
-        (void)hipFree(c->bwd_ws);
-        c->bwd_ws = nullptr;
-        c->bwd_ws_bytes = 0;
-        hipError_t e = hipMalloc(&c->bwd_ws, ws_bytes);
-        if (e != hipSuccess) return e;
-        c->bwd_ws_bytes = ws_bytes;
-    }
+    const BwdLayout W = bwd_layout(c, K);
+    hipError_t e0 = ensure_bwd_workspace(c, W);
+    if (e0 != hipSuccess) return e0;
     char *ws = (char *)c->bwd_ws;
     void *final_state = ws;
-    auto step_buf = [&](int64_t k) -> void * { return ws + o_steps + (size_t)k * up256(sbytes); };
-    double *lamC = (double *)(ws + o_lam);
-    void *rid = ws + o_rid;
-    void *adj = ws + o_adj;
-    double *tacc = use_tacc ? (double *)(ws + o_tacc) : nullptr;
+    auto step_buf = [&](int64_t k) -> void * { return ws + W.o_steps + (size_t)k * W.step_bytes; };
+    double *lamC = (double *)(ws + W.o_lam);
+    void *rid = ws + W.o_rid;
+    void *adj = ws + W.o_adj;
+    double *tacc = W.tbytes ? (double *)(ws + W.o_tacc) : nullptr;
     const bool fp64 = c->form == ST_FORM_FP64;
 
     // an error return first drains the stream
@@ -644,8 +673,8 @@ hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd,
                        lamC);
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(3 * ncell)), dim3(256), 0, s, dU, 3 * ncell);
     if (tacc)
-        hipLaunchKernelGGL(k_zero_f64, dim3(grid_of((int64_t)(tbytes / 8))), dim3(256), 0, s,
-                           tacc, (int64_t)(tbytes / 8));
+        hipLaunchKernelGGL(k_zero_f64, dim3(grid_of((int64_t)(W.tbytes / 8))), dim3(256), 0, s,
+                           tacc, (int64_t)(W.tbytes / 8));
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_of(P * (int64_t)c->tsize)), dim3(256), 0, s,
                        (double *)rid, P * (int64_t)c->tsize);
     e = hipGetLastError();

@@ -450,6 +450,33 @@ st_status st_tape_clear(st_ctx *c)
     return ST_OK;
 }
 
+st_status st_tape_reserve(st_ctx *c, int32_t tape, int64_t substeps)
+{
+    if (!c) return ST_ERR_INVALID;
+    if (tape <= 0 || substeps < 0)
+        return fail(c, ST_ERR_INVALID, "st_tape_reserve: tape must be > 0 and substeps >= 0");
+    if (c->form == ST_FORM_FP32)
+        return fail(c, ST_ERR_INVALID,
+                    "st_tape_reserve: taped steps need the FP64 or FP32 chunk-local form");
+    if (!c->tape.empty()) return fail(c, ST_ERR_STATE, "st_tape_reserve: a tape is recorded");
+    try {
+        ST_HIP(hipSetDevice(c->device));
+        const int64_t need = (substeps + tape - 1) / tape;
+        while ((int64_t)c->spare.size() < need) {
+            st::Snapshot sn;
+            sn.bytes = st::snapshot_bytes(c);
+            if (hipMalloc(&sn.buf, sn.bytes) != hipSuccess)
+                return fail(c, ST_ERR_OOM, "st_tape_reserve: checkpoint");
+            c->spare.push_back(sn);
+        }
+        if (st::reserve_backward(c, tape) != hipSuccess)
+            return fail(c, ST_ERR_OOM, "st_tape_reserve: backward workspace");
+        return ST_OK;
+    } catch (...) {
+        return fail(c, ST_ERR_OOM, "st_tape_reserve: host allocation failed");
+    }
+}
+
 st_status st_backward(st_ctx *c, const double *dL_dSint, double *dL_du, double *dL_dd,
                       void *hip_stream)
 {

@@ -229,6 +229,8 @@ hipError_t launch_ec(st_ctx *c, int kind, const double *S_last, double *applied,
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 size_t snapshot_bytes(const st_ctx *c);
 hipError_t launch_backward(st_ctx *c, const double *lam, double *dU, double *dd, hipStream_t s);
+// allocates st_backward's workspace for checkpoints every K sub-steps, if smaller
+hipError_t reserve_backward(st_ctx *c, int64_t K);
 hipError_t launch_hilbert_positions(int32_t order, int64_t nseg, int64_t seg_begin,
                                     int64_t per_seg, const double L[3], int64_t first, int64_t n,
                                     const double *u, double *x, hipStream_t s);

@@ -221,6 +221,11 @@ class Tracker:
         N.check(N.lib().st_tape_clear(self.ctx), self.ctx)
         self._taped = []
 
+    def tape_reserve(self, tape, substeps):
+        """Allocate the buffers of a taped run of `substeps` sub-steps (checkpoint
+        every `tape`) and of its backward ahead of the run."""
+        N.check(N.lib().st_tape_reserve(self.ctx, int(tape), int(substeps)), self.ctx)
+
     def run_coupled(self, u0, cs, dt, timed=True):
         """Coupled run with the rotating field; returns (field_ms, step_ms, total_ms)."""
         assert u0.is_cuda and u0.dtype == self.field_dtype and tuple(u0.shape) == self.field_shape

@@ -106,6 +106,7 @@ def test_null_arguments(N):
     assert L.st_inject(None, 1, None, None, None, 0, None) == N.ST_ERR_INVALID
     assert L.st_get_sources(None, None, 0, 0, None) == N.ST_ERR_INVALID
     assert L.st_backward(None, None, None, None, None) == N.ST_ERR_INVALID
+    assert L.st_tape_reserve(None, 20, 200) == N.ST_ERR_INVALID
     assert L.st_count(None, None) == N.ST_ERR_INVALID
 
 

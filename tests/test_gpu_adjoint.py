@@ -301,6 +301,47 @@ def test_repeated_taped_runs_reuse_buffers(form):
     b.close()
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32_local"])
+def test_tape_reserve(form):
+    """st_tape_reserve allocates a taped run's checkpoints and its backward's
+    workspace ahead: the run and its gradients match those of a tracker that
+    allocates as it goes (checkpoints every 3 of 8 steps, and a second run
+    with more checkpoints than were reserved), and reserving is refused
+    while a tape is recorded and for invalid intervals."""
+    import torch
+    from paper_2603_26691_amd._native import STError
+    w = _case(P=3000, nsteps=8)
+    x, up, d = w.particles()
+    Udev, _ = fields(w, form)
+    lam = None
+    for K, reserve in ((3, w.nsteps), (2, 4)):
+        a = tracker(w, form)
+        a.inject(x, up, d)
+        a.tape_reserve(K, reserve)
+        b = tracker(w, form)
+        b.inject(x, up, d)
+        for k in range(w.nsteps):
+            a.step(Udev, w.dt, tape=K)
+            b.step(Udev, w.dt, tape=K)
+            if k == 0:
+                with pytest.raises(STError):
+                    a.tape_reserve(K, w.nsteps)   # a tape is recorded
+        Sa, Sb = a.sources(), b.sources()
+        # (the deposit's additions are ordered by atomics)
+        assert float((Sa - Sb).norm() / Sb.norm()) < 1e-12
+        if lam is None:
+            lam = torch.sin(Sa * 1e3).contiguous()
+        ga = [g.cpu().numpy() for g in a.backward(lam)]
+        gb = [g.cpu().numpy() for g in b.backward(lam)]
+        tol = 1e-12 if form == "fp64" else 1e-6
+        assert _rel(ga[0], gb[0]) < tol and _rel(ga[1], gb[1]) < tol, K
+        for bad in ((0, 8), (3, -1)):
+            with pytest.raises(STError):
+                a.tape_reserve(*bad)
+        a.close()
+        b.close()
+
+
 def test_adjoint_against_finite_differences():
     """Central differences of the GPU's own FP64 forward (h = 1e-3 relative
     for diameters, 1e-3 m/s for field entries) on 32 sampled entries."""
