@@ -359,7 +359,8 @@ __global__ void k_fold_tiles(const double *tacc, Params p, int64_t C, double *Ub
 
 // Nearest grid point: the reverse of each particle adds its ufbar to its
 // cell of the tile with one LDS atomic per component, in the state
-// precision; per chunk each tile cell's sum goes to dL/du with one atomic.
+// precision; per chunk each tile cell's sum goes to the chunk's binary64 tile
+// sums (or, for a chunk split over several items, to dL/du with one atomic).
 template <class T, int E>
 __global__ void __launch_bounds__(kAdjBlock) k_adjoint_ngp(AdjArgs<T> a)
 {
@@ -398,9 +399,14 @@ __global__ void __launch_bounds__(kAdjBlock) k_adjoint_ngp(AdjArgs<T> a)
         for (int k = 0; k < 7; ++k) rec[k] = (T)rc[k];
     }
     __syncthreads();
+    // a chunk that is one work item adds its sums to those it keeps over the
+    // steps; a chunk split over several items adds them to dL/du atomically
+    const bool own = a.tacc != nullptr && a.cnt[c] <= kSeg;
     for (int t = threadIdx.x; t < 3 * S3; t += kAdjBlock) {
         const double v = (double)ubt[t];
-        if (v != 0.0) {
+        if (own) {
+            a.tacc[c * 3 * S3 + t] += v;
+        } else if (v != 0.0) {
             const int comp = t / S3;
             atomicAdd(a.Ubar + comp * ncell + tile_cell<E>(p, cx, cy, cz, t - comp * S3), v);
         }
@@ -593,9 +599,9 @@ namespace {
 // One workspace, kept in the context for the next call: the state the
 // forward run ended in, the saved states of one segment (K - 1 steps; the
 // newest is the store itself), dL/dS by chunk, the adjoint records by id and
-// those of the current segment by anchor, and the trilinear kernel's
-// per-chunk tile sums of dL/du when they fit in a GiB (else each step adds
-// its sums to dL/du atomically).
+// those of the current segment by anchor, and the per-chunk tile sums of
+// dL/du when they fit in a GiB (else each step adds its sums to dL/du
+// atomically).
 struct BwdLayout {
     size_t step_bytes, o_steps, o_lam, o_rid, o_adj, o_tacc, tbytes, bytes;
 };
@@ -615,7 +621,7 @@ BwdLayout bwd_layout(const st_ctx *c, int64_t K)
     W.o_adj = W.o_rid + up256((size_t)(P > 0 ? P : 1) * rbytes);
     W.o_tacc = W.o_adj + up256((size_t)c->slots * rbytes);
     W.tbytes = (size_t)c->C * 3 * S3 * 8;
-    if (c->prm.interp != 0 || W.tbytes > ((size_t)1 << 30)) W.tbytes = 0;
+    if (W.tbytes > ((size_t)1 << 30)) W.tbytes = 0;
     W.bytes = W.o_tacc + W.tbytes;
     return W;
 }
