@@ -23,14 +23,17 @@
 // Checkpoints of the particle store are kept every `tape_every` taped steps;
 // each segment is recomputed from its checkpoint (deposit off), each step
 // saving the state it starts from, the ids and its layout as it streams
-// them, and then reversed newest first.
-// The per-particle adjoint state is kept in one 64-byte record per particle,
-// indexed within a segment by the particle's slot in the segment's
-// checkpoint (its anchor): the restored checkpoint's ids are replaced by the
-// slot indices before the recomputation, so every saved step carries anchors
-// instead of ids, and since particles that stay in their chunk keep their
-// slots, each step reads and writes the records nearly in slot order.
-// Between segments the records pass through an array by particle id.
+// them, and then reversed newest first (the newest from the store itself).
+// The per-particle adjoint state is kept in one record of eight values of
+// the state precision per particle, indexed within a segment by the
+// particle's slot in the segment's checkpoint (its anchor): the restored
+// checkpoint's ids are replaced by the slot indices before the
+// recomputation, so every saved step carries anchors instead of ids, and
+// since particles that stay in their chunk keep their slots, each step reads
+// and writes the records nearly in slot order.  Between segments the records
+// of particles whose slot changed pass through an array by particle id.
+// The tile sums of dL/du of a chunk that is one work item are kept per chunk
+// over all the reversed steps and added to dL/du once at the end.
 #include "st_internal.h"
 
 #include <math.h>
