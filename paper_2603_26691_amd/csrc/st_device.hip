@@ -1269,28 +1269,26 @@ __device__ void arrive(const RebinArgs<T> &a)
     const View<T> &V = a.V;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // a thread's first mover is read together with the count (the list's
-    // entries below its capacity can all be read), each next one while the
-    // current one is placed
+    // a thread's first destination and rank are read together with the
+    // count (the list's entries below its capacity can all be read), the
+    // next ones while the current mover is placed; a record is read beside
+    // its destination's counts
     int32_t c = 0, r = 0;
-    MoverRec<T> rec{};
     if (m < a.mcap) {
         c = a.mv.dest[m];
         r = a.mv.rank[m];
-        rec = a.mv.rec[m];
     }
     const int64_t nm = a.flags[nmov_slot(a.epoch)];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.flags[F_DEAD] = 0;   // summed by the counts
     for (; m < nm; m += stride) {
+        const MoverRec<T> cur = a.mv.rec[m];
         const int64_t base = V.base[c];
         const int32_t h = V.ndead[c] + a.out_cnt[c];
         const int64_t slot = r < h ? base + a.hole[base + h - 1 - r]
                                    : base + V.cnt[c] + (r - h);
-        const MoverRec<T> cur = rec;
         if (m + stride < nm && m + stride < a.mcap) {
             c = a.mv.dest[m + stride];
             r = a.mv.rank[m + stride];
-            rec = a.mv.rec[m + stride];
         }
         V.ox[slot] = cur.ox;
         V.oy[slot] = cur.oy;
