@@ -377,6 +377,34 @@ def test_adjoint_across_full_rebins(orc, form, tol):
     assert eU < tol and ed < tol
 
 
+@pytest.mark.parametrize("E", [2, 4])
+@pytest.mark.parametrize("interp", ["trilinear", "ngp"])
+def test_adjoint_small_chunks(orc, E, interp):
+    """Chunks of 2^3 and 4^3 cells (their own tile sizes, node sums and fold
+    of the per-chunk sums into dL/du), FP64 form, against the oracle
+    adjoint."""
+    import dataclasses
+    import torch
+    w = dataclasses.replace(_case(P=4000), chunk_edge=E)
+    x, up, d = w.particles()
+    Udev, Uor = fields(w, "fp64")
+    t = tracker(w, "fp64", interp=interp)
+    t.inject(x, up, d)
+    s0 = state(t)
+    for _ in range(w.nsteps):
+        t.step(Udev, w.dt, tape=7)
+    S = t.sources()
+    lam = torch.sin(S * 1e3).contiguous()
+    dU, dd = (g.cpu().numpy() for g in t.backward(lam))
+    t.close()
+    mesh = oracle_mesh(w, interp=1 if interp == "ngp" else 0)
+    oU, od = orc.adjoint(mesh, Uor, s0["x"], s0["up"], s0["d"], w.dt, w.nsteps,
+                         lam.cpu().numpy())
+    print(E, interp, "adjoint rel L2: dU", _rel(dU, oU), "dd", _rel(dd, od))
+    _entrywise(dU, oU, "fp64", "dL/du")
+    _entrywise(dd, od, "fp64", "dL/dd")
+
+
 def test_adjoint_against_finite_differences():
     """Central differences of the GPU's own FP64 forward (h = 1e-3 relative
     for diameters, 1e-3 m/s for field entries) on 32 sampled entries."""
